@@ -1,0 +1,209 @@
+/*
+ * libcvx: per-pixel ray casting of volumetric canvases stored as arrays of
+ * deep octrees, with front-to-back RGBA compositing, on one MI355X (gfx950).
+ *
+ * Source of the operations (CanvoX, Kim et al., arXiv:1704.02724):
+ *  - canvas = uniform array of R^3 octree roots, each refinable to a large
+ *    depth (Sec. 4);
+ *  - pointer-free linear pools indexed by cell id; a refined cell always has
+ *    8 consecutive children and only parent and first child are stored
+ *    (Sec. 4.1.1, "Tree Graph G_p"); three outer-face neighbours per cell are
+ *    derived from that tree on the GPU (Sec. 4.1.1 "Neighbor Graph G_3" and
+ *    Sec. 4.1.2);
+ *  - rays start from an eye kept in full precision (Sec. 6.1), are traversed
+ *    in cell-local coordinates from face to face using the neighbour graph and
+ *    accumulate colour until full opacity or canvas exit (Sec. 6.2-6.3).
+ *
+ * Conventions
+ *  - Child octant numbering: x | y<<1 | z<<2 (the sibling across the x face of
+ *    child 0 is child 1).
+ *  - Canvas positions are measured in root-edge units: q = (p - origin) /
+ *    root_edge, so the canvas is [0, R]^3 and a depth-d cell has edge 2^-d.
+ *  - Pixel (x, y), row 0 at the top, unit direction in FP64:
+ *      u = (2(x+1/2)/W - 1) tan_half_fov_x,  v = (1 - 2(y+1/2)/H) tan_half_fov_y,
+ *      d = normalize(fwd + u right + v up).
+ *  - Compositing: emission-absorption through piecewise-constant leaves.  A
+ *    leaf holds colour c and kappa = optical depth across one leaf edge; a
+ *    segment of length l leaf edges does T' = T exp(-kappa l),
+ *    C += (T - T') c, T = T'.  Output RGBA = (C, 1 - T), premultiplied,
+ *    black background.  alpha_stop >= 1 disables early termination;
+ *    otherwise a ray stops after the segment where 1 - T >= alpha_stop.
+ *
+ * Errors: every entry point returns CVX_OK (0) or a negative CVX_ERR_* code;
+ * no C++ exception crosses this boundary.  A failed call leaves previously
+ * uploaded pools unchanged.  A context is bound to one HIP device and one
+ * stream and is not thread-safe.
+ */
+#ifndef CVX_H
+#define CVX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CVX_OK 0
+#define CVX_ERR_INVALID_ARG (-1)
+#define CVX_ERR_BAD_POOL (-2)
+#define CVX_ERR_OOM (-3)
+#define CVX_ERR_HIP (-4)
+#define CVX_ERR_NOT_FOUND (-5)
+
+#define CVX_LEAF_RGBA8_F16 0u /* {u8 r,g,b,a; u16 kappa (IEEE half); u16 pad}, 8 bytes */
+#define CVX_LEAF_F64 1u       /* {double r,g,b,kappa}, 32 bytes */
+
+#define CVX_VARIANT_FP32_REBASED 0u /* FP32 cell-local traversal, FP64 rebase */
+#define CVX_VARIANT_FP64_PLAIN 1u   /* FP64 canvas-global traversal and compositing */
+#define CVX_VARIANT_FP32_NAIVE 2u   /* FP32 canvas-global traversal (drifts at depth) */
+
+#define CVX_MAX_CANVASES 64
+#define CVX_MAX_DEPTH 30
+#define CVX_MAX_VIEWS 4096
+
+/* Per-ray flag bits reported by trace mode. */
+#define CVX_RAYFLAG_STEP_CAP 1u    /* watchdog: traversal stopped at max steps */
+#define CVX_RAYFLAG_FP64_EXIT 2u   /* an exit decision needed the FP64 fallback */
+#define CVX_RAYFLAG_BAD_LINK 4u    /* a neighbour link was null inside the canvas */
+
+typedef struct cvx_ctx cvx_ctx;
+
+/* Canvas description.  The canvas covers origin + [0, R*root_edge]^3. */
+typedef struct {
+  double origin[3];
+  double root_edge;     /* > 0 */
+  uint32_t R;           /* roots per axis, 1..64 */
+  uint32_t max_depth;   /* deepest level present, <= CVX_MAX_DEPTH; R * 2^max_depth <= 2^31 */
+  uint32_t leaf_format; /* CVX_LEAF_* */
+  uint32_t reserved;    /* must be 0 */
+} cvx_canvas_desc;
+
+/* Tree node (Sec. 4.1.1 G_p).  child: bit 31 set -> leaf, low 31 bits index
+ * the leaf array; otherwise the first of 8 consecutive children, a multiple
+ * of 8.  parent: index of the parent, 0xffffffff for roots.  Roots are nodes
+ * [0, R^3) in x-fastest order; slots [R^3, roundup8(R^3)) are padding and are
+ * ignored.  Nodes not reachable from the roots are ignored. */
+typedef struct {
+  uint32_t child;
+  uint32_t parent;
+} cvx_node;
+
+typedef struct {
+  uint8_t r, g, b, a; /* colour byte/255 (linear); a is not read by the renderer */
+  uint16_t kappa_f16; /* optical depth across one leaf edge, IEEE half, >= 0, finite */
+  uint16_t pad;
+} cvx_leaf_rgba8_f16;
+
+typedef struct {
+  double r, g, b, kappa; /* kappa >= 0, finite */
+} cvx_leaf_f64;
+
+/* One pinhole view.  right, up, fwd: orthonormal (|dot| and |norm-1| below
+ * 1e-9).  Its W*H pixels are written to out[(out_offset_px + y*W + x)]. */
+typedef struct {
+  int32_t canvas_id;
+  uint32_t W, H;
+  float alpha_stop; /* in (0, 1]; >= 1 disables early termination */
+  double eye[3];
+  double right[3], up[3], fwd[3];
+  double tan_half_fov_x, tan_half_fov_y; /* > 0 */
+  uint64_t out_offset_px;
+} cvx_view;
+
+/* Trace mode: only the listed rays are traced and, for each, the visited
+ * leaves (node ids of the uploaded pool, in front-to-back order), their local
+ * segment lengths l and the final RGBA are written.  All pointers are device
+ * pointers owned by the caller.  Zero-length segments are not recorded. */
+typedef struct {
+  uint64_t n;              /* number of rays */
+  const uint64_t* ray_ids; /* (view index << 32) | (y*W + x) */
+  uint32_t max_leaves;     /* capacity per ray of leaf_ids / local_len */
+  uint32_t reserved;
+  uint32_t* leaf_ids;      /* n * max_leaves */
+  float* local_len;        /* n * max_leaves, may be NULL */
+  double* local_len64;     /* n * max_leaves, may be NULL */
+  uint32_t* n_leaves;      /* n: total segments (may exceed max_leaves) */
+  uint32_t* flags;         /* n: CVX_RAYFLAG_* */
+  float* rgba;             /* 4n */
+} cvx_trace;
+
+/* Render options.  Zero means "default" for every tuning field. */
+typedef struct {
+  uint32_t variant;     /* CVX_VARIANT_* */
+  uint32_t tile_w;      /* pixel tile width; tile_w * tile_h must be 64 (one wavefront) */
+  uint32_t tile_h;
+  uint32_t workgroups;  /* persistent grid size */
+  uint32_t wg_size;     /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  uint32_t use_graph;   /* 1: capture the launch in a HIP graph and replay it */
+  uint32_t out_f64;     /* FP64_PLAIN only: out is double RGBA instead of float */
+  uint32_t reserved;
+  const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
+  uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
+} cvx_render_opts;
+
+#define CVX_STAT_RAYS 0        /* rays traced */
+#define CVX_STAT_LEAVES 1      /* positive-length leaf segments */
+#define CVX_STAT_OUTER 2       /* transitions through an outer face (neighbour link read) */
+#define CVX_STAT_DESCENT 3     /* tree levels descended (first leaf depth + depth increases) */
+#define CVX_STAT_FP64_EXIT 4   /* exit decisions taken by the FP64 fallback */
+#define CVX_STAT_REBASE 5      /* FP64 rebases of the cell-local point */
+#define CVX_STAT_COUNT 8
+
+/* Create a context on HIP device `hip_device` that enqueues on `hip_stream`
+ * (a hipStream_t, borrowed; NULL = the null stream).  Device memory is
+ * allocated per uploaded pool and per render configuration. */
+int cvx_create(cvx_ctx** ctx, int hip_device, void* hip_stream);
+
+/* Upload a canvas pool (Sec. 4.1.1-4.1.2): host arrays are read during the
+ * call only.  The pool is validated (indices in range, children groups
+ * 8-aligned, each node reached once, parents consistent, depth <= max_depth,
+ * leaf indices < n_leaves, finite non-negative kappa), re-laid out on the
+ * device into 16-byte node records plus a node-indexed payload array, and
+ * the three outer-face neighbour links per node are built on the GPU level
+ * by level.  Replaces any pool under canvas_id only on success.  Returns
+ * CVX_ERR_BAD_POOL for an invalid pool, CVX_ERR_OOM when the device lacks
+ * room (checked before any allocation). Synchronous. */
+int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
+                    const cvx_node* nodes, uint64_t n_nodes, const void* leaves,
+                    uint64_t n_leaves);
+
+/* Render n_views views into out_dev (a device buffer of at least
+ * max(out_offset_px + W*H) RGBA pixels, float unless opts->out_f64).
+ * Asynchronous on the context stream; the caller synchronises.  The views
+ * array is copied before return.  Every pixel is computed by one lane in a
+ * fixed order, so the output does not depend on scheduling or tuning. */
+int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+               const cvx_render_opts* opts);
+
+/* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
+int cvx_free_pool(cvx_ctx* ctx, int canvas_id);
+
+/* Release everything owned by the context (waits for its stream). */
+void cvx_destroy(cvx_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char* cvx_last_error(cvx_ctx* ctx);
+
+/* Static name of a status code. */
+const char* cvx_status_str(int status);
+
+/* Host-only validation of a pool, the same checks cvx_upload_pool makes.
+ * Writes a message into msg (may be NULL). Touches no GPU. */
+int cvx_validate_pool(const cvx_canvas_desc* desc, const cvx_node* nodes, uint64_t n_nodes,
+                      const void* leaves, uint64_t n_leaves, char* msg, size_t msg_len);
+
+/* Host-only validation of views against the given canvas descriptions
+ * (canvases[i] may be NULL for an absent canvas).  Touches no GPU. */
+int cvx_validate_views(const cvx_view* views, int n_views,
+                       const cvx_canvas_desc* const* canvases, int n_canvases, char* msg,
+                       size_t msg_len);
+
+/* Device bytes held by the pool under canvas_id. */
+int cvx_pool_bytes(cvx_ctx* ctx, int canvas_id, uint64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CVX_H */

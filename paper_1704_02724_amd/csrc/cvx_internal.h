@@ -1,0 +1,94 @@
+// Internal declarations shared by the libcvx translation units.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cvx.h"
+
+#define CVX_LEAF_BIT 0x80000000u
+#define CVX_NONE 0xffffffffu
+
+namespace cvx {
+
+// Breadth-first order of the reachable nodes, one range per level.
+struct PoolPlan {
+  std::vector<uint32_t> order;
+  std::vector<uint64_t> level_off;  // level d is order[level_off[d], level_off[d+1])
+  uint32_t depth = 0;               // deepest level present
+};
+
+int check_desc(const cvx_canvas_desc* d, std::string& msg);
+int validate_pool(const cvx_canvas_desc* desc, const cvx_node* nodes, uint64_t n_nodes,
+                  const void* leaves, uint64_t n_leaves, PoolPlan* plan, std::string& msg);
+int validate_views(const cvx_view* views, int n_views, const cvx_canvas_desc* const* canvases,
+                   int n_canvases, std::string& msg);
+
+// Device node record (16 bytes), one per pool node, indexed like the input:
+//   x: leaf -> 1 | depth << 1 ; refined -> index of the first child (multiple of 8, even)
+//   y, z, w: outer-face neighbour on the x, y, z axis: the cell of the same
+//            depth across the face of the parent that this child touches, or
+//            the coarser leaf covering it; CVX_NONE outside the canvas or for roots.
+// Payload (indexed by node id): RGBA8 + half kappa (uint2) or 4 doubles.
+struct DevCanvas {
+  bool present = false;
+  cvx_canvas_desc desc{};
+  uint64_t n_nodes = 0;
+  uint32_t depth = 0;     // deepest level present
+  void* rec = nullptr;    // uint4 per node
+  void* pay = nullptr;    // uint2 or double4 per node
+  uint64_t bytes = 0;
+};
+
+// Per-view parameters in device memory (host computes them once per render).
+struct DView {
+  const void* rec;
+  const void* pay;
+  uint32_t R, fmt, max_depth, tiles_x;
+  double o[3];          // eye in root-edge units
+  double right[3], up[3], fwd[3];
+  double tan_x, tan_y;
+  uint32_t W, H;
+  uint64_t out_off;
+  uint64_t first_tile;  // prefix sum of tile counts over the views
+  float alpha_stop;
+  uint32_t max_steps;
+};
+
+// Launch-invariant header in device memory, so a captured graph can be
+// replayed for any view set of the same launch shape.
+struct CastHeader {
+  uint64_t total_work;  // tiles (render) or 64-ray chunks (trace)
+  uint64_t n_rays;      // trace mode: number of listed rays
+  uint32_t n_views;
+  uint32_t queue;       // work-queue head, reset by a kernel before each cast
+};
+
+struct CastArgs {
+  const DView* views;
+  CastHeader* hdr;
+  void* out;
+  const cvx_trace* trace_host;  // unused on device
+  // trace mode
+  const uint64_t* ray_ids;
+  uint32_t max_leaves;
+  uint32_t* leaf_ids;
+  float* local_len;
+  double* local_len64;
+  uint32_t* n_leaves;
+  uint32_t* flags;
+  float* trace_rgba;
+  uint64_t* stats;
+  uint32_t tile_w, tile_h;
+};
+
+// kernel launchers (cvx_upload.hip, cvx_cast.hip); return a hipError_t value
+int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, uint64_t end,
+                          uint32_t level, const void* raw_nodes, const void* raw_leaves,
+                          uint32_t fmt, void* rec, void* pay, uint32_t R);
+int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out_f64,
+                const CastArgs& a, uint32_t workgroups, uint32_t wg_size);
+int launch_reset(void* stream, CastHeader* hdr);
+
+}  // namespace cvx

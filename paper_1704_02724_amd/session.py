@@ -1,0 +1,111 @@
+"""Convenience wrapper over the C-ABI: torch supplies device memory and the stream.
+
+Marshalling only: uploads hand host arrays to ``cvx_upload_pool``; renders
+allocate the output (or trace buffers) as torch tensors on the current device
+and call ``cvx_render`` on torch's current stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cvx
+
+
+class Session:
+    def __init__(self, device: int = 0):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libcvx needs a HIP device")
+        self.torch = torch
+        torch.cuda.set_device(device)
+        self.device = torch.device("cuda", device)
+        # a stream of our own (default priority): graph capture needs a
+        # non-null stream; it is ordered against torch's current stream
+        self.stream = torch.cuda.Stream(self.device)
+        self.ctx = cvx.cvx_create(device, self.stream.cuda_stream)
+        self.descs = {}
+
+    def close(self):
+        if self.ctx:
+            cvx.cvx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- pools ------------------------------------------------------------
+    def upload(self, canvas_id, canvas):
+        d = cvx.make_desc(canvas.origin, canvas.root_edge, canvas.R, canvas.max_depth,
+                          canvas.leaf_format)
+        cvx.cvx_upload_pool(self.ctx, canvas_id, d, canvas.nodes, canvas.leaves)
+        self.descs[canvas_id] = d
+
+    def free(self, canvas_id):
+        cvx.cvx_free_pool(self.ctx, canvas_id)
+        self.descs.pop(canvas_id, None)
+
+    # -- stream ordering ----------------------------------------------------
+    def _enter(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _leave(self, *tensors):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        for t in tensors:
+            t.record_stream(self.stream)
+
+    # -- render -----------------------------------------------------------
+    def out_pixels(self, views):
+        return max(v["out_offset_px"] + v["W"] * v["H"] for v in views)
+
+    def render(self, views, variant="fp32_rebased", out=None, out_f64=False, stats=None,
+               **tuning):
+        torch = self.torch
+        n_px = self.out_pixels(views)
+        if out is None:
+            out = torch.empty((n_px, 4), dtype=torch.float64 if out_f64 else torch.float32,
+                              device=self.device)
+        varr = cvx.make_views(views)
+        opts = cvx.make_opts(variant, out_f64=out_f64,
+                             stats_ptr=stats.data_ptr() if stats is not None else 0, **tuning)
+        self._enter()
+        cvx.cvx_render(self.ctx, varr, out.data_ptr(), opts)
+        self._leave(out, *([stats] if stats is not None else []))
+        return out
+
+    def new_stats(self):
+        return self.torch.zeros(cvx.CVX_STAT_COUNT, dtype=self.torch.int64, device=self.device)
+
+    def trace(self, views, ray_ids, max_leaves=256, variant="fp32_rebased", len64=False):
+        torch = self.torch
+        ids = torch.from_numpy(np.ascontiguousarray(ray_ids, dtype=np.uint64).view(np.int64))
+        ids = ids.to(self.device)
+        n = len(ray_ids)
+        leaf_ids = torch.zeros((n, max(max_leaves, 1)), dtype=torch.int32, device=self.device)
+        llen = torch.zeros((n, max(max_leaves, 1)),
+                           dtype=torch.float64 if len64 else torch.float32, device=self.device)
+        nl = torch.zeros(n, dtype=torch.int32, device=self.device)
+        fl = torch.zeros(n, dtype=torch.int32, device=self.device)
+        rgba = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
+        tr = cvx.cvx_trace()
+        tr.n = n
+        tr.ray_ids = ids.data_ptr()
+        tr.max_leaves = max_leaves
+        tr.leaf_ids = leaf_ids.data_ptr()
+        tr.local_len = None if len64 else llen.data_ptr()
+        tr.local_len64 = llen.data_ptr() if len64 else None
+        tr.n_leaves = nl.data_ptr()
+        tr.flags = fl.data_ptr()
+        tr.rgba = rgba.data_ptr()
+        varr = cvx.make_views(views)
+        opts = cvx.make_opts(variant, trace=tr)
+        self._enter()
+        cvx.cvx_render(self.ctx, varr, 0, opts)
+        self._leave(ids, leaf_ids, llen, nl, fl, rgba)
+        torch.cuda.synchronize(self.device)
+        return dict(leaf_ids=leaf_ids.cpu().numpy().view(np.uint32), local_len=llen.cpu().numpy(),
+                    n_leaves=nl.cpu().numpy().view(np.uint32), flags=fl.cpu().numpy().view(np.uint32),
+                    rgba=rgba.cpu().numpy())

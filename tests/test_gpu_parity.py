@@ -1,0 +1,243 @@
+"""GPU parity: the C-ABI HIP path against the CPU FP64 oracle on seeded inputs.
+
+Bars (see the tolerance notes next to each check):
+  * leaf sequences: bit-exact node ids and counts for every ray the oracle
+    does not flag (within 1e-12 of a face of a visited leaf, or an ambiguous
+    stop), for FP32_REBASED and FP64_PLAIN;
+  * RGBA: <= 1e-3 absolute for the FP32 variants (FP16/RGBA8 leaves, FP32
+    accumulators); FP64_PLAIN against the oracle within a bound derived from
+    FP64 rounding of canvas-global parameters (see tol64);
+  * FP32_NAIVE has no bar: its mismatch count is the expected failure.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from canvasgen import LEAF_F64, LEAF_RGBA8_F16, make_view, stereo_pair
+from canvasgen import configs, trees
+from oracle import oracle
+
+from gpu_common import all_ray_ids, compare_traces, rgba_err, sample_ray_ids
+
+pytestmark = pytest.mark.gpu
+
+RGBA_TOL32 = 1e-3
+
+
+def tol64(depth):
+    # canvas-global FP64: t carries ~4 ulp of |t| <= 4 root edges, so a local
+    # length l = dt * 2^depth differs by <= 2^-49 * 2^depth between two FP64
+    # evaluations; with optical depth kappa <= 64 per leaf edge this bounds
+    # the transmittance difference.
+    return max(1e-11, 64.0 * 2.0 ** (depth - 49))
+
+
+@pytest.fixture(scope="module")
+def sess():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_02724_amd.session import Session
+    s = Session(0)
+    yield s
+    s.close()
+
+
+def _views_around(rng, n, W, H, inside=True, R=1.0):
+    vs, off = [], 0
+    for _ in range(n):
+        e = rng.uniform(0.05 * R, 0.95 * R, 3) if inside else rng.uniform(-1.0, 2.0, 3) * R
+        tgt = rng.uniform(0.2 * R, 0.8 * R, 3)
+        vs.append(make_view(e, tgt - e, rng.uniform(0.3, 1.2), W, H, out_offset_px=off))
+        off += W * H
+    return vs
+
+
+def _check(sess, canvases, views, variant, max_leaves=512, rgba_tol=RGBA_TOL32, out64=False,
+           min_checked=0.9):
+    for i, c in enumerate(canvases):
+        sess.upload(i, c)
+    ids = all_ray_ids(views)
+    orc = oracle.render(canvases, views, ids, max_leaves=max_leaves)
+    gpu = sess.trace(views, ids, max_leaves, variant, len64=out64)
+    assert np.all((gpu["flags"] & 0x5) == 0), "step cap or broken link on a valid pool"
+    cmp = compare_traces(orc, gpu, max_leaves)
+    ok = cmp["ok_mask"]
+    assert ok.mean() >= min_checked, cmp
+    img = sess.render(views, variant, out_f64=out64).cpu().numpy()
+    pix = np.concatenate([v["out_offset_px"] + np.arange(v["W"] * v["H"]) for v in views])
+    err = rgba_err(img[pix], orc["rgba"], ok)
+    # trace mode and render mode run the same per-ray code
+    if not out64:
+        np.testing.assert_array_equal(gpu["rgba"], img[pix].astype(np.float32))
+    return cmp, err
+
+
+@pytest.mark.parametrize("R,depth,seed", [(1, 5, 1), (2, 4, 2), (3, 4, 3), (1, 8, 4)])
+def test_random_trees_fp64_plain(sess, R, depth, seed):
+    cv = trees.random_tree(R, depth, seed=seed, p_split=0.5, max_nodes=8000, leaf_format=LEAF_F64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    views = _views_around(rng, 3, 24, 20, inside=True, R=1.0) + \
+        [make_view((-0.6, 0.4, 1.7), (1.0, 0.1, -1.0), 0.8, 17, 31, out_offset_px=3 * 480)]
+    cmp, err = _check(sess, [cv], views, "fp64_plain", out64=True)
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= tol64(depth), err
+
+
+@pytest.mark.parametrize("R,depth,seed", [(1, 5, 11), (2, 5, 12), (1, 9, 13)])
+def test_random_trees_fp32_rebased(sess, R, depth, seed):
+    cv = trees.random_tree(R, depth, seed=seed, p_split=0.5, max_nodes=8000,
+                           leaf_format=LEAF_RGBA8_F16, kappa_range=(0.0, 8.0))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    views = _views_around(rng, 4, 23, 19, inside=seed % 2 == 0)
+    cmp, err = _check(sess, [cv], views, "fp32_rebased")
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert cmp["len_bad"] == 0, cmp
+    assert err <= RGBA_TOL32, err
+
+
+@pytest.mark.parametrize("depth", [16, 24, 30])
+def test_deep_paths(sess, depth):
+    """Long same-depth runs next to abrupt jumps of up to `depth` levels."""
+    t = np.array([0.3 + 1 / 3000, 0.6 - 1 / 7000, 0.45 + 1 / 5000])
+    cv = trees.deep_path_tree(depth, target=t, seed=depth, leaf_format=LEAF_RGBA8_F16, halo=2,
+                              kappa_range=(0.0, 3.0))
+    h = 2.0 ** -depth
+    views = [
+        make_view(t + h * np.array([-6.3, 0.37, 0.71]), (1.0, 0.05, -0.02), 0.7, 31, 29),
+        make_view(t + h * np.array([0.2, 0.1, -0.3]), (0.3, -0.8, 0.5), 1.5, 27, 25,
+                  out_offset_px=31 * 29),
+        make_view((-0.5, 0.55, 0.2), t - np.array([-0.5, 0.55, 0.2]), 3 * h, 25, 21,
+                  out_offset_px=31 * 29 + 27 * 25),
+    ]
+    cmp, err = _check(sess, [cv], views, "fp32_rebased")
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= RGBA_TOL32, err
+    cmp64, err64 = _check(sess, [cv], views, "fp64_plain")
+    assert cmp64["seq_mismatch"] == 0, cmp64
+    assert err64 <= RGBA_TOL32, err64
+    naive, _ = _check(sess, [cv], views, "fp32_naive", min_checked=0.0)
+    print(f"depth {depth}: naive FP32 sequence mismatches {naive['seq_mismatch']} of {naive['n']}")
+
+
+def test_tiny_config_fp64_everywhere(sess):
+    w = configs.tiny(leaf_format=LEAF_F64)
+    cmp, err = _check(sess, w.canvases, w.views, "fp64_plain", max_leaves=128, out64=True)
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= tol64(12), err
+    print(f"tiny fp64: flagged {cmp['flagged']} of {cmp['n']}, max rgba err {err:.3g}")
+
+
+def test_tiny_config_fp32(sess):
+    w = configs.tiny(leaf_format=LEAF_RGBA8_F16)
+    cmp, err = _check(sess, w.canvases, w.views, "fp32_rebased", max_leaves=128)
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= RGBA_TOL32, err
+    naive, nerr = _check(sess, w.canvases, w.views, "fp32_naive", max_leaves=128, min_checked=0.0)
+    print(f"tiny fp32: flagged {cmp['flagged']}, rgba err {err:.3g}; naive mismatches "
+          f"{naive['seq_mismatch']}, naive rgba err {nerr:.3g}")
+
+
+def test_determinism_across_tuning(sess):
+    w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=101, H=77)
+    sess.upload(0, w.canvases[0])
+    ref = sess.render(w.views, "fp32_rebased").cpu().numpy()
+    for tile, wgs, wg in [((16, 4), 1, 64), ((64, 1), 7, 128), ((4, 16), 0, 256), ((32, 2), 3, 256)]:
+        img = sess.render(w.views, "fp32_rebased", tile=tile, workgroups=wgs, wg_size=wg)
+        np.testing.assert_array_equal(img.cpu().numpy(), ref)
+
+
+def test_graph_replay_matches_eager(sess):
+    torch = sess.torch
+    w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=64, H=48)
+    sess.upload(0, w.canvases[0])
+    v2 = [dict(w.views[0], eye=(0.45, 0.52, -0.6))]
+    eager1 = sess.render(w.views, "fp32_rebased").cpu().numpy()
+    eager2 = sess.render(v2, "fp32_rebased").cpu().numpy()
+    out = torch.empty((64 * 48, 4), dtype=torch.float32, device=sess.device)
+    for i in range(4):
+        vs, ref = (w.views, eager1) if i % 2 == 0 else (v2, eager2)
+        out.fill_(-1.0)
+        sess.render(vs, "fp32_rebased", out=out, use_graph=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+        _ = (torch.ones(1000, device=sess.device) * 2).sum().item()  # eager work in between
+
+
+def test_multi_canvas_offsets_ragged(sess):
+    a = trees.random_tree(1, 6, seed=21, max_nodes=6000, leaf_format=LEAF_RGBA8_F16)
+    b = trees.random_tree(2, 5, seed=22, max_nodes=6000, leaf_format=LEAF_RGBA8_F16)
+    views = [make_view((0.5, 0.5, -1.0), (0.01, 0.02, 1.0), 0.6, 37, 23, canvas_id=0),
+             make_view((0.3, 0.2, 0.4), (0.5, 0.2, 0.3), 1.0, 1, 1, canvas_id=1,
+                       out_offset_px=2000),
+             make_view((1.5, 0.5, 0.5), (-1.0, 0.1, 0.05), 0.9, 64, 9, canvas_id=0,
+                       out_offset_px=37 * 23)]
+    cmp, err = _check(sess, [a, b], views, "fp32_rebased")
+    assert cmp["seq_mismatch"] == 0 and err <= RGBA_TOL32, (cmp, err)
+
+
+def test_alpha_stop(sess):
+    cv = trees.random_tree(1, 6, seed=31, max_nodes=8000, leaf_format=LEAF_RGBA8_F16,
+                           kappa_range=(0.5, 4.0))
+    rng = np.random.Generator(np.random.PCG64(31))
+    views = _views_around(rng, 2, 20, 20, inside=False)
+    for v in views:
+        v["alpha_stop"] = 0.9
+    cmp, err = _check(sess, [cv], views, "fp32_rebased")
+    assert cmp["seq_mismatch"] == 0 and err <= RGBA_TOL32, (cmp, err)
+    cmp64, err64 = _check(sess, [cv], views, "fp64_plain")
+    assert cmp64["seq_mismatch"] == 0, cmp64
+
+
+def test_miss_gives_zero(sess):
+    cv = trees.uniform_tree(1, 2, seed=1, leaf_format=LEAF_RGBA8_F16)
+    sess.upload(0, cv)
+    v = [make_view((-1.0, 0.5, 0.5), (-1.0, 0.0, 0.0), 0.5, 8, 8)]
+    for var in ("fp32_rebased", "fp64_plain", "fp32_naive"):
+        img = sess.render(v, var).cpu().numpy()
+        assert np.all(img == 0.0)
+
+
+def test_stats_match_oracle_counts(sess):
+    cv = trees.random_tree(1, 7, seed=41, max_nodes=8000, leaf_format=LEAF_RGBA8_F16)
+    rng = np.random.Generator(np.random.PCG64(41))
+    views = _views_around(rng, 2, 32, 32, inside=True)
+    sess.upload(0, cv)
+    orc = oracle.render([cv], views)
+    if np.any(orc["flags"]):
+        pytest.skip("seeded views hit a flagged ray")
+    for var in ("fp32_rebased", "fp64_plain"):
+        st = sess.new_stats()
+        sess.render(views, var, stats=st)
+        s = st.cpu().numpy()
+        assert s[0] == 2 * 32 * 32
+        assert s[1] == orc["n_leaves"].sum()
+        links = (orc["alg_bytes"] - 16 - 8 * orc["n_leaves"].astype(np.float64)) / 4
+        assert s[2] + s[3] == links.sum()
+
+
+def test_error_paths(sess):
+    from paper_1704_02724_amd import cvx
+    cv = trees.random_tree(1, 4, seed=51, leaf_format=LEAF_RGBA8_F16)
+    sess.upload(5, cv)
+    v = [make_view((0.5, 0.5, -1.0), (0.0, 0.0, 1.0), 0.5, 8, 8, canvas_id=5)]
+    ref = sess.render(v).cpu().numpy()
+    bad = trees.random_tree(1, 4, seed=51, leaf_format=LEAF_RGBA8_F16)
+    bad.nodes[int(bad.nodes[0, 0]) + 3, 1] = 7  # wrong parent
+    with pytest.raises(cvx.CvxError) as e:
+        sess.upload(5, bad)
+    assert e.value.code == cvx.CVX_ERR_BAD_POOL
+    np.testing.assert_array_equal(sess.render(v).cpu().numpy(), ref)  # old pool intact
+    with pytest.raises(cvx.CvxError) as e:
+        sess.render([dict(v[0], canvas_id=9)])
+    assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+    f64 = trees.random_tree(1, 4, seed=52, leaf_format=LEAF_F64)
+    sess.upload(6, f64)
+    with pytest.raises(cvx.CvxError) as e:
+        sess.render([dict(v[0], canvas_id=6)], "fp32_rebased")
+    assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+    sess.free(6)
+    with pytest.raises(cvx.CvxError) as e:
+        sess.free(6)
+    assert e.value.code == cvx.CVX_ERR_NOT_FOUND
