@@ -36,6 +36,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1704_02724_amd/csrc/cvx_cast.hip", "paper_1704_02724_amd/csrc/cvx_internal.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(variant, workload):
+    """HBM bytes per launch from the committed rocprofv3 summary of this kernel
+    and workload, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_cast_{variant}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def build_workload(name, threads):
     from canvasgen import configs
     if name == "depth24":
@@ -96,6 +124,9 @@ def main():
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--wg-size", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this size (a reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the ray caster has no "
@@ -122,6 +153,16 @@ def main():
         sess.upload(i, c)
     log(f"uploaded in {time.perf_counter() - t:.1f}s")
 
+    if args.copy_probe_mb:
+        nb = args.copy_probe_mb << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=sess.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes read + {nb} bytes written")
+        del src, dst
+
     # --- timed: production variant
     out, wall, per = time_variant(sess, views, args.variant, args.steps, args.warmup, tuning)
     ms_step = wall * 1e3 / args.steps
@@ -136,6 +177,7 @@ def main():
     alg_bytes = 16.0 * s[0] + 8.0 * s[1] + 4.0 * (s[2] + s[3])
     kernel_s = per.mean() * 1e-3
     achieved = alg_bytes / kernel_s
+    traffic_b = profiled_traffic(args.variant, args.workload)
 
     # --- FP64 plain baseline on the same GPU
     fp64 = None
@@ -209,7 +251,8 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK, 4),
-            "traffic": None,
+            "traffic": (round(traffic_b / kernel_s / 1e9, 1) if traffic_b else None),
+            "traffic_bytes_per_launch": traffic_b,
             "alg_bytes_per_launch": alg_bytes,
             "alg_bytes_per_ray": alg_bytes / max(s[0], 1.0),
             "alg_bytes_per_ray_oracle_sample": mean_b_oracle,

@@ -114,7 +114,8 @@ typedef struct {
 /* Trace mode: only the listed rays are traced and, for each, the visited
  * leaves (node ids of the uploaded pool, in front-to-back order), their local
  * segment lengths l and the final RGBA are written.  All pointers are device
- * pointers owned by the caller.  Zero-length segments are not recorded. */
+ * pointers owned by the caller.  Every visited leaf is recorded, also when
+ * its length rounds to 0 in the variant's precision. */
 typedef struct {
   uint64_t n;              /* number of rays */
   const uint64_t* ray_ids; /* (view index << 32) | (y*W + x) */
@@ -134,7 +135,7 @@ typedef struct {
   uint32_t tile_w;      /* pixel tile width; tile_w * tile_h must be 64 (one wavefront) */
   uint32_t tile_h;
   uint32_t workgroups;  /* persistent grid size */
-  uint32_t wg_size;     /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  uint32_t wg_size;     /* threads per workgroup: 64, 128 or 256 */
   uint32_t use_graph;   /* 1: capture the launch in a HIP graph and replay it */
   uint32_t out_f64;     /* FP64_PLAIN only: out is double RGBA instead of float */
   uint32_t reserved;
@@ -143,7 +144,7 @@ typedef struct {
 } cvx_render_opts;
 
 #define CVX_STAT_RAYS 0        /* rays traced */
-#define CVX_STAT_LEAVES 1      /* positive-length leaf segments */
+#define CVX_STAT_LEAVES 1      /* visited leaves (segments composited) */
 #define CVX_STAT_OUTER 2       /* transitions through an outer face (neighbour link read) */
 #define CVX_STAT_DESCENT 3     /* tree levels descended (first leaf depth + depth increases) */
 #define CVX_STAT_FP64_EXIT 4   /* exit decisions taken by the FP64 fallback */

@@ -214,7 +214,10 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
         if (tt < best) { best = tt; kx = k; Xb = X; }
       }
       float len = (best - t_ent) * ldexpf(1.0f, (int)dep);
-      if (len > 0.0f) {
+      len = len > 0.0f ? len : 0.0f;
+      // every visited leaf is recorded: for a ray not within the face band of
+      // a visited leaf the exact segment is positive even when it rounds to 0
+      {
         float col[3], kap;
         decode8(pay, col, kap);
         float Tn = T * __expf(-kap * len);
@@ -302,7 +305,8 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
         if (tt < best) { best = tt; kx = k; }
       }
       double len = ldexp(best - t_ent, (int)dep);
-      if (len > 0.0) {
+      len = len > 0.0 ? len : 0.0;
+      {
         double col[3], kap;
         if (v.fmt == CVX_LEAF_F64) {
           double4 p = ((const double4*)v.pay)[I];
@@ -434,7 +438,9 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
         if (STATS) acc.fp64_exit++;
       }
       len = len > 0.0f ? len : 0.0f;
-      if (len > 0.0f) {
+      // every visited leaf is recorded: for a ray not within the face band of
+      // a visited leaf the exact segment is positive even when it rounds to 0
+      {
         float col[3], kap;
         decode8(pay, col, kap);
         float Tn = T * __expf(-kap * len);
