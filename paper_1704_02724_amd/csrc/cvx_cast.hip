@@ -12,20 +12,13 @@
 // point (Sec. 4.1.1, first child + octant).  Colour accumulates front to back
 // until the ray leaves the canvas or reaches the stop opacity.
 //
-// Three variants share the integer bookkeeping (node id, depth, integer cell
-// coordinates at that depth, which makes every face plane an exact dyadic):
-//  FP32_REBASED  cell-local FP32 point p in [-0.5,0.5]^3 (Sec. 6.1-6.3: origin
-//                at the cell centre, edge 1).  Exit lengths t_k =
-//                (+-0.5 - p_k)/d_k in FP32 with a running error bound on p in
-//                the spirit of the per-step analysis of Sec. 6.3; an exit
-//                decision whose margin is below the bound is re-taken in FP64
-//                from the exact face planes.  On every descent, after such a
-//                fallback, or once the bound has grown, p is rebuilt from the
-//                FP64 ray at the exactly known crossing plane ("rebase").
-//                Same-depth steps only flip p on the exit axis; steps into a
-//                coarser leaf rescale p by a power of two.
-//  FP64_PLAIN    canvas-global FP64: exit t from the exact face planes, FP64
-//                compositing.  The GPU baseline.
+// All variants share the integer bookkeeping: node id, depth and the integer
+// coordinates of the cell at that depth, which make every face plane an exact
+// dyadic.  Per-axis state lives in V3 structs (never in arrays indexed by a
+// run-time axis) so that it stays in registers.
+//  FP32_REBASED  cell-local FP32 DDA with certified decisions (cast_fp32).
+//  FP64_PLAIN    canvas-global FP64: exit t from the exact face planes each
+//                step, FP64 compositing.  The GPU baseline.
 //  FP32_NAIVE    canvas-global FP32 (the paper's "canvas coordinate"
 //                traversal that drifts at depth); kept to show the failure.
 #include <hip/hip_runtime.h>
@@ -37,117 +30,31 @@ namespace cvx {
 namespace {
 
 constexpr float BIGF = 1e30f;
-constexpr float EP_MAX = 0x1p-14f;  // rebase once the point error bound exceeds this
+
+template <class T>
+struct V3 {
+  T x, y, z;
+};
+
+// Component k of v; k is a run-time axis (compiles to selects) or a constant.
+// v is taken by value: a select between loads of one object would otherwise
+// be folded into a variable-offset load, which forces the struct into memory.
+template <class T>
+__device__ __forceinline__ T get(V3<T> v, int k) {
+  T r = v.x;
+  r = k == 1 ? v.y : r;
+  r = k == 2 ? v.z : r;
+  return r;
+}
+template <class T>
+__device__ __forceinline__ void set(V3<T>& v, int k, T a) {
+  const V3<T> u = v;
+  v = V3<T>{k == 0 ? a : u.x, k == 1 ? a : u.y, k == 2 ? a : u.z};
+}
 
 struct Acc {
   uint32_t rays, leaves, outer, descent, fp64_exit, rebase;
 };
-
-// Runtime-indexed access to 3-element register arrays without private memory.
-template <class T>
-__device__ __forceinline__ T pick(const T a[3], int k) {
-  return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
-}
-template <class T>
-__device__ __forceinline__ void put(T a[3], int k, T v) {
-  a[0] = k == 0 ? v : a[0];
-  a[1] = k == 1 ? v : a[1];
-  a[2] = k == 2 ? v : a[2];
-}
-
-__device__ __forceinline__ void ray_dir(const DView& v, uint32_t x, uint32_t y, double d[3]) {
-#pragma clang fp contract(off)
-  double u = (2.0 * ((double)x + 0.5) / (double)v.W - 1.0) * v.tan_x;
-  double w = (1.0 - 2.0 * ((double)y + 0.5) / (double)v.H) * v.tan_y;
-  double n2 = 0.0;
-  for (int k = 0; k < 3; ++k) {
-    d[k] = v.fwd[k] + u * v.right[k];
-    d[k] = d[k] + w * v.up[k];
-    n2 += d[k] * d[k];
-  }
-  double n = __builtin_sqrt(n2);
-  for (int k = 0; k < 3; ++k) d[k] = d[k] / n;
-}
-
-struct Entry {
-  double t0, t1;
-  int kin, side;
-  bool hit;
-};
-
-// Slab test of the ray against the canvas box [0, R]^3 (FP64).
-__device__ __forceinline__ Entry canvas_entry(const double o[3], const double d[3], double Rd) {
-  Entry e;
-  double tin = -__builtin_inf(), tout = __builtin_inf();
-  int kin = -1, side = 0;
-  bool miss = false;
-  for (int k = 0; k < 3; ++k) {
-    if (d[k] != 0.0) {
-      double ta = (0.0 - o[k]) / d[k], tb = (Rd - o[k]) / d[k];
-      double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
-      if (lo > tin) {
-        tin = lo;
-        kin = k;
-        side = d[k] > 0.0 ? 0 : 1;
-      }
-      if (hi < tout) tout = hi;
-    } else if (o[k] < 0.0 || o[k] > Rd) {
-      miss = true;
-    }
-  }
-  e.t0 = tin > 0.0 ? tin : 0.0;
-  e.t1 = tout;
-  e.kin = tin > 0.0 ? kin : -1;
-  e.side = side;
-  e.hit = !miss && e.t0 < e.t1;
-  return e;
-}
-
-__device__ __forceinline__ uint4 ld_rec(const void* rec, uint32_t i) {
-  return ((const uint4*)rec)[i];
-}
-
-// Descend from the current cell (r refined) to the leaf containing q; on a
-// mid-plane the child on the side the ray moves into is taken.
-template <class Real>
-__device__ __forceinline__ void descend(const void* rec, const Real q[3], const bool up[3],
-                                        uint32_t& I, uint32_t& dep, uint32_t c[3], uint4& r) {
-  while (!(r.x & 1u)) {
-    Real h = (Real)ldexp(1.0, -(int)dep);
-    uint32_t oct = 0;
-    for (int k = 0; k < 3; ++k) {
-      Real mid = ((Real)c[k] + (Real)0.5) * h;
-      uint32_t b = (q[k] > mid) || (q[k] == mid && up[k]);
-      oct |= b << k;
-      c[k] = 2u * c[k] + b;
-    }
-    I = r.x + oct;
-    ++dep;
-    r = ld_rec(rec, I);
-  }
-}
-
-// Root cell containing q (ties go to the side the ray moves into).
-template <class Real>
-__device__ __forceinline__ void root_of(const Real q[3], const bool up[3], uint32_t R,
-                                        uint32_t c[3], uint32_t& I) {
-  for (int k = 0; k < 3; ++k) {
-    Real f = floor(q[k]);
-    int n = (int)f;
-    if (q[k] == f && !up[k]) n -= 1;
-    n = n < 0 ? 0 : n;
-    n = n > (int)R - 1 ? (int)R - 1 : n;
-    c[k] = (uint32_t)n;
-  }
-  I = c[0] + R * (c[1] + R * c[2]);
-}
-
-__device__ __forceinline__ void decode8(uint2 p, float col[3], float& kap) {
-  col[0] = (float)(p.x & 0xffu) * (1.0f / 255.0f);
-  col[1] = (float)((p.x >> 8) & 0xffu) * (1.0f / 255.0f);
-  col[2] = (float)((p.x >> 16) & 0xffu) * (1.0f / 255.0f);
-  kap = (float)__builtin_bit_cast(_Float16, (unsigned short)(p.y & 0xffffu));
-}
 
 struct Out {
   double rgba[4];
@@ -163,369 +70,573 @@ struct Sink {
   uint32_t cap;
 };
 
-template <int VAR, bool TRACE, bool STATS>
-__device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out) {
-  double d[3];
-  ray_dir(v, px, py, d);
-  const double o[3] = {v.o[0], v.o[1], v.o[2]};
+__device__ __forceinline__ void record(Sink& sk, uint32_t n, uint32_t I, double len) {
+  if (n < sk.cap) {
+    sk.ids[n] = I;
+    if (sk.len32) sk.len32[n] = (float)len;
+    if (sk.len64) sk.len64[n] = len;
+  }
+}
+
+// FP64 unit direction of pixel (x, y); the exact operation order of the
+// public convention, no contraction.
+__device__ __forceinline__ V3<double> ray_dir(const DView& v, uint32_t x, uint32_t y) {
+#pragma clang fp contract(off)
+  double u = (2.0 * ((double)x + 0.5) / (double)v.W - 1.0) * v.tan_x;
+  double w = (1.0 - 2.0 * ((double)y + 0.5) / (double)v.H) * v.tan_y;
+  double d[3], n2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    d[k] = v.fwd[k] + u * v.right[k];
+    d[k] = d[k] + w * v.up[k];
+    n2 += d[k] * d[k];
+  }
+  double n = __builtin_sqrt(n2);
+  return V3<double>{d[0] / n, d[1] / n, d[2] / n};
+}
+
+struct Entry {
+  double t0, t1;
+  int kin, side;
+  bool hit;
+};
+
+// Slab test of the ray against the canvas box [0, R]^3 (FP64).
+__device__ __forceinline__ Entry canvas_entry(const V3<double>& o, const V3<double>& d, double Rd) {
+  Entry e;
+  double tin = -__builtin_inf(), tout = __builtin_inf();
+  int kin = -1, side = 0;
+  bool miss = false;
+  for (int k = 0; k < 3; ++k) {
+    const double dk = get(d, k), ok = get(o, k);
+    if (dk != 0.0) {
+      double ta = (0.0 - ok) / dk, tb = (Rd - ok) / dk;
+      double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+      if (lo > tin) {
+        tin = lo;
+        kin = k;
+        side = dk > 0.0 ? 0 : 1;
+      }
+      if (hi < tout) tout = hi;
+    } else if (ok < 0.0 || ok > Rd) {
+      miss = true;
+    }
+  }
+  e.t0 = tin > 0.0 ? tin : 0.0;
+  e.t1 = tout;
+  e.kin = tin > 0.0 ? kin : -1;
+  e.side = side;
+  e.hit = !miss && e.t0 < e.t1;
+  return e;
+}
+
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) u32x4_t* grec_t;
+typedef const __attribute__((address_space(1))) u32x2_t* gpay_t;
+
+// Pool loads through the global address space (the pointers come from the
+// view table, so the compiler would otherwise emit flat loads).
+__device__ __forceinline__ uint4 ld_rec(const void* rec, uint32_t i) {
+  const u32x4_t x = ((grec_t)rec)[i];
+  return make_uint4(x.x, x.y, x.z, x.w);
+}
+__device__ __forceinline__ uint2 ld_pay(const void* pay, uint32_t i) {
+  const u32x2_t x = ((gpay_t)pay)[i];
+  return make_uint2(x.x, x.y);
+}
+
+// Descend from the current cell (r refined) to the leaf containing q; on a
+// mid-plane the child on the side the ray moves into is taken.
+template <class Real>
+__device__ __forceinline__ void descend(const void* rec, const V3<Real>& q, const V3<bool>& up,
+                                        uint32_t& I, uint32_t& dep, V3<uint32_t>& c, uint4& r) {
+  while (!(r.x & 1u)) {
+    const Real h = (Real)ldexp(1.0, -(int)dep);
+    uint32_t oct = 0;
+    for (int k = 0; k < 3; ++k) {
+      const Real mid = ((Real)get(c, k) + (Real)0.5) * h;
+      const Real qk = get(q, k);
+      const uint32_t b = (qk > mid) || (qk == mid && get(up, k));
+      oct |= b << k;
+      set(c, k, 2u * get(c, k) + b);
+    }
+    I = r.x + oct;
+    ++dep;
+    r = ld_rec(rec, I);
+  }
+}
+
+// Root cell containing q (ties go to the side the ray moves into).
+template <class Real>
+__device__ __forceinline__ void root_of(const V3<Real>& q, const V3<bool>& up, uint32_t R,
+                                        V3<uint32_t>& c, uint32_t& I) {
+  for (int k = 0; k < 3; ++k) {
+    const Real qk = get(q, k);
+    const Real f = floor(qk);
+    int n = (int)f;
+    if (qk == f && !get(up, k)) n -= 1;
+    n = n < 0 ? 0 : n;
+    n = n > (int)R - 1 ? (int)R - 1 : n;
+    set(c, k, (uint32_t)n);
+  }
+  I = c.x + R * (c.y + R * c.z);
+}
+
+// Neighbour across the exit face on axis kx: the sibling (inner face, index
+// arithmetic), the next root (root array), or the stored outer-face link.
+struct Move {
+  uint32_t N, nc;
+  bool at_edge, outer;
+};
+
+__device__ __forceinline__ Move neighbour(const DView& v, uint32_t I, const uint4 r, uint32_t dep,
+                                          uint32_t ck, bool upk, int kx) {
+  Move m;
+  m.at_edge = upk ? (ck + 1u >= (v.R << dep)) : (ck == 0u);
+  m.nc = upk ? ck + 1u : ck - 1u;
+  const bool root = dep == 0;
+  const bool inner = !root && ((ck & 1u) == (upk ? 0u : 1u));
+  uint32_t rstride = 1u;
+  rstride = kx == 1 ? v.R : rstride;
+  rstride = kx == 2 ? v.R * v.R : rstride;
+  const uint32_t stride = root ? rstride : (1u << kx);
+  const uint32_t sib = upk ? I + stride : I - stride;
+  uint32_t link = r.y;
+  link = kx == 1 ? r.z : link;
+  link = kx == 2 ? r.w : link;
+  m.N = (root || inner) ? sib : link;
+  m.outer = !inner;
+  return m;
+}
+
+__device__ __forceinline__ float kappa_of(uint2 p) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(p.y & 0xffffu));
+}
+
+// ----------------------------------------------------------------------------
+// FP32_REBASED: cell-local FP32 traversal (Sec. 6.1-6.2) as a certified DDA.
+//
+// After a rebase at the entry point p0 (ray parameter te) of a cell, lengths
+// are measured in "base units", the edge of a cell of depth db (a few levels
+// below the current leaf), from p0: s = (t - te) / h_db.  For every axis k the
+// face plane of the current leaf that lies ahead of the ray (its far plane in
+// the travel direction) is held as an exact integer offset N_k, in base cells,
+// from the far plane of the rebase cell, whose s-value S0_k was computed in
+// FP64.  The far plane's s-value is S_k = S0_k + N_k / |d_k| with a constant
+// error bound (no drift with the number of steps, unlike the per-step update
+// analysed in Sec. 6.3):
+//   |S_k - exact| <= ALPHA (S0_k + |N_k| / |d_k|) + beta,  beta = 2^(db-50) tR,
+// ALPHA covering the FP32 roundings of S0, 1/|d|, N and the fused update.
+// Exit = argmin S_k, certified when the other two exceed it by more than the
+// sum of their bounds; otherwise the FP64 face planes decide.  A same-depth
+// step adds the cell width w = 2^(db-dep) to N on the exit axis; a step into a
+// coarser leaf adds the integer distance to its far planes; a refined cell is
+// descended one level per iteration by comparing the entry s with the
+// mid-plane s-values (certified likewise).  FP64 rebuilds the state
+// ("rebase") only at the ray's start, after an FP64 decision, or when a
+// descent goes below db or cannot be certified.
+// ----------------------------------------------------------------------------
+constexpr float ALPHA = 0x1p-21f;
+// certification bound per plane value: 1.0625 (ALPHA G + beta) plus the 2^-23 G
+// rounding of the FP32 difference (G >= |value|), folded into one fma
+constexpr float ALPHA_C = 0x1p-21f * 1.0625f + 0x1p-23f;
+constexpr float BETA_C = 1.0625f;
+constexpr uint32_t DB_MARGIN = 8;
+
+template <bool TRACE, bool STATS>
+__device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
+                          Sink sk, Acc& acc, Out& out) {
+  const V3<double> o{v.o[0], v.o[1], v.o[2]};
   const double Rd = (double)v.R;
   const void* rec = v.rec;
-  out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
-  out.flags = 0;
-  out.n = 0;
-  if (STATS) acc.rays++;
-  Entry en = canvas_entry(o, d, Rd);
-  if (!en.hit) return;
-  const bool up[3] = {d[0] > 0.0, d[1] > 0.0, d[2] > 0.0};
-  const bool use_stop = v.alpha_stop < 1.0f;
-  uint32_t n_rec = 0;
-
-  // ---------------------------------------------------------------- FP32 naive
-  if constexpr (VAR == (int)CVX_VARIANT_FP32_NAIVE) {
-    float of[3], df[3], idf[3];
-    bool par[3];
-    for (int k = 0; k < 3; ++k) {
-      of[k] = (float)o[k];
-      df[k] = (float)d[k];
-      par[k] = df[k] == 0.0f;
-      idf[k] = par[k] ? 0.0f : 1.0f / df[k];
-    }
-    float t_ent = (float)en.t0;
-    float q[3];
-    for (int k = 0; k < 3; ++k) q[k] = of[k] + t_ent * df[k];
-    if (en.kin >= 0) put(q, en.kin, en.side ? (float)Rd : 0.0f);
-    uint32_t I, dep = 0, c[3];
-    root_of<float>(q, up, v.R, c, I);
-    uint4 r = ld_rec(rec, I);
-    descend<float>(rec, q, up, I, dep, c, r);
-    if (STATS) acc.descent += dep;
-    float T = 1.0f, C[3] = {0.f, 0.f, 0.f};
-    uint2 pay = ((const uint2*)v.pay)[I];
-    for (uint32_t step = 0;; ++step) {
-      if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
-      float h = ldexpf(1.0f, -(int)dep);
-      float best = BIGF;
-      int kx = 0;
-      float Xb = 0.f;
-      for (int k = 0; k < 3; ++k) {
-        if (par[k]) continue;
-        float X = (float)(c[k] + (up[k] ? 1u : 0u)) * h;
-        float tt = (X - of[k]) * idf[k];
-        if (tt < best) { best = tt; kx = k; Xb = X; }
-      }
-      float len = (best - t_ent) * ldexpf(1.0f, (int)dep);
-      len = len > 0.0f ? len : 0.0f;
-      // every visited leaf is recorded: for a ray not within the face band of
-      // a visited leaf the exact segment is positive even when it rounds to 0
-      {
-        float col[3], kap;
-        decode8(pay, col, kap);
-        float Tn = T * __expf(-kap * len);
-        float a = T - Tn;
-        for (int k = 0; k < 3; ++k) C[k] = __builtin_fma(a, col[k], C[k]);
-        T = Tn;
-        if (TRACE && n_rec < sk.cap) { sk.ids[n_rec] = I; if (sk.len32) sk.len32[n_rec] = len; if (sk.len64) sk.len64[n_rec] = len; }
-        ++n_rec;
-        if (use_stop && 1.0f - T >= v.alpha_stop) break;
-      }
-      const uint32_t ck = pick(c, kx);
-      const bool upk = pick(up, kx);
-      const uint32_t side_n = v.R << dep;
-      if (upk ? (ck + 1u >= side_n) : (ck == 0u)) break;
-      const uint32_t nc = upk ? ck + 1u : ck - 1u;
-      uint32_t N;
-      bool outer;
-      if (dep == 0) {
-        uint32_t stride = kx == 0 ? 1u : (kx == 1 ? v.R : v.R * v.R);
-        N = upk ? I + stride : I - stride;
-        outer = true;
-      } else if ((ck & 1u) == (upk ? 0u : 1u)) {
-        N = upk ? I + (1u << kx) : I - (1u << kx);
-        outer = false;
-      } else {
-        N = kx == 0 ? r.y : (kx == 1 ? r.z : r.w);
-        outer = true;
-      }
-      if (N == CVX_NONE) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
-      if (STATS) acc.outer += outer;
-      put(c, kx, nc);
-      uint4 rN = ld_rec(rec, N);
-      I = N;
-      r = rN;
-      if (r.x & 1u) {
-        uint32_t dN = (r.x >> 1) & 63u;
-        if (dN < dep) {
-          for (int k = 0; k < 3; ++k) c[k] >>= (dep - dN);
-          dep = dN;
-        }
-      } else {
-        for (int k = 0; k < 3; ++k) q[k] = of[k] + best * df[k];
-        put(q, kx, Xb);
-        uint32_t d0 = dep;
-        descend<float>(rec, q, up, I, dep, c, r);
-        if (STATS) acc.descent += dep - d0;
-      }
-      pay = ((const uint2*)v.pay)[I];
-      t_ent = best > t_ent ? best : t_ent;
-    }
-    out.rgba[0] = C[0];
-    out.rgba[1] = C[1];
-    out.rgba[2] = C[2];
-    out.rgba[3] = 1.0f - T;
-    out.n = n_rec;
-    if (STATS) acc.leaves += n_rec;
-    return;
+  const void* payp = v.pay;
+  V3<double> inv;
+  V3<float> tD;
+  for (int k = 0; k < 3; ++k) {
+    const double dk = get(d, k);
+    set(inv, k, 1.0 / dk);
+    set(tD, k, __builtin_fabs(dk) >= 0x1p-60 ? 1.0f / __builtin_fabsf((float)dk) : 0.0f);
   }
+  const bool anypar = tD.x == 0.0f || tD.y == 0.0f || tD.z == 0.0f;
+  const float tR = (float)(en.t1 + Rd + 1.0);
+  const bool use_stop = v.alpha_stop < 1.0f;
 
-  double inv[3];
-  for (int k = 0; k < 3; ++k) inv[k] = 1.0 / d[k];
-  double q[3];
-  for (int k = 0; k < 3; ++k) q[k] = o[k] + en.t0 * d[k];
-  if (en.kin >= 0) put(q, en.kin, en.side ? Rd : 0.0);
-  for (int k = 0; k < 3; ++k) q[k] = q[k] < 0.0 ? 0.0 : (q[k] > Rd ? Rd : q[k]);
-  uint32_t I, dep = 0, c[3];
+  // first leaf: FP64 point location from the root
+  V3<double> q;
+  for (int k = 0; k < 3; ++k) {
+    double qk = get(o, k) + en.t0 * get(d, k);
+    if (k == en.kin) qk = en.side ? Rd : 0.0;
+    set(q, k, qk < 0.0 ? 0.0 : (qk > Rd ? Rd : qk));
+  }
+  uint32_t I, dep = 0;
+  V3<uint32_t> c;
+  root_of<double>(q, up, v.R, c, I);
+  uint4 r = ld_rec(rec, I);
+  uint2 pay = make_uint2(0u, 0u);
+
+  uint32_t db = 0, w = 1;
+  V3<float> S0{0.f, 0.f, 0.f};
+  V3<int32_t> Nk{0, 0, 0};
+  float s_ent = 0.0f, e_ent = 0.0f, beta = 0.0f;
+  // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
+  // current cell I is descended first when it is refined.
+  auto rebase = [&](double te) __attribute__((always_inline)) {
+    const uint32_t d0 = dep;
+    descend<double>(rec, q, up, I, dep, c, r);
+    if (STATS) acc.descent += dep - d0;
+    pay = ld_pay(payp, I);
+    db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
+    w = 1u << (db - dep);
+    const double hd = ldexp(1.0, -(int)dep);
+    for (int k = 0; k < 3; ++k) {
+      const double X = (double)(get(c, k) + (get(up, k) ? 1u : 0u)) * hd;
+      const double Tk = (X - get(o, k)) * get(inv, k);
+      set(S0, k, get(tD, k) == 0.0f ? BIGF : (float)ldexp(Tk - te, (int)db));
+    }
+    Nk = V3<int32_t>{0, 0, 0};
+    s_ent = 0.0f;
+    beta = ldexpf(tR, (int)db - 50);
+    e_ent = beta;
+    if (STATS) acc.rebase++;
+  };
+  rebase(en.t0);
+
+  float T = 1.0f;
+  V3<float> C{0.f, 0.f, 0.f};
+  uint32_t n_rec = 0;
+  int ke = en.kin;  // axis of the face the current cell was entered through
+  for (uint32_t step = 0;; ++step) {
+    if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    bool need64 = false;
+    if (!(r.x & 1u)) {
+      // ---- refined cell entered through its near face on axis ke: one level
+      need64 = w < 2u || ke < 0 || anypar;
+      const uint32_t half = w >> 1;
+      uint32_t oct = 0;
+      V3<uint32_t> b3;
+      V3<int32_t> dN;
+      for (int k = 0; k < 3; ++k) {
+        const float Nm = (float)(get(Nk, k) - (int32_t)half);
+        const float M = __builtin_fmaf(Nm, get(tD, k), get(S0, k));
+        const float eM = __builtin_fmaf(
+            ALPHA, __builtin_fmaf(__builtin_fabsf(Nm), get(tD, k), get(S0, k)), beta);
+        const float diff = s_ent - M;
+        const bool isk = k == ke;
+        const bool far = !isk && diff >= 0.0f;
+        const bool sure = __builtin_fabsf(diff) > (e_ent + eM) * 1.0625f +
+                                                      0x1p-23f * __builtin_fmaxf(__builtin_fabsf(M), s_ent);
+        need64 = need64 || (!isk && !sure);
+        const uint32_t b = (get(up, k) == far) ? 1u : 0u;
+        set(b3, k, b);
+        set(dN, k, far ? 0 : (int32_t)half);
+        oct |= b << k;
+      }
+      if (!need64) {
+        for (int k = 0; k < 3; ++k) {
+          set(Nk, k, get(Nk, k) - get(dN, k));
+          set(c, k, 2u * get(c, k) + get(b3, k));
+        }
+        I = r.x + oct;
+        ++dep;
+        w = half;
+        r = ld_rec(rec, I);
+        pay = ld_pay(payp, I);
+        if (STATS) acc.descent++;
+        continue;
+      }
+    } else {
+      // ---- leaf: exit face, certified against the error bounds
+      V3<float> S, eb;
+      const float betac = beta * BETA_C;
+      for (int k = 0; k < 3; ++k) {
+        const float Nf = (float)get(Nk, k);
+        set(S, k, __builtin_fmaf(Nf, get(tD, k), get(S0, k)));
+        set(eb, k, __builtin_fmaf(ALPHA_C, __builtin_fmaf(__builtin_fabsf(Nf), get(tD, k), get(S0, k)),
+                                  betac));
+      }
+      const float Smin = __builtin_fminf(S.x, __builtin_fminf(S.y, S.z));
+      int kx = 2;
+      kx = S.y == Smin ? 1 : kx;
+      kx = S.x == Smin ? 0 : kx;
+      const float emin = get(eb, kx);
+      uint32_t nsure = 0;
+      for (int k = 0; k < 3; ++k) nsure += (get(S, k) - Smin > get(eb, k) + emin) ? 1u : 0u;
+      if (nsure != 2u) {
+        // FP64 decision from the exact face planes
+        const double hd = ldexp(1.0, -(int)dep);
+        double best = __builtin_inf();
+        int kb = kx;
+        for (int k = 0; k < 3; ++k) {
+          const double X = (double)(get(c, k) + (get(up, k) ? 1u : 0u)) * hd;
+          const double tt = get(d, k) == 0.0 ? __builtin_inf() : (X - get(o, k)) * get(inv, k);
+          kb = tt < best ? k : kb;
+          best = tt < best ? tt : best;
+        }
+        kx = kb;
+        need64 = true;
+        out.flags |= CVX_RAYFLAG_FP64_EXIT;
+        if (STATS) acc.fp64_exit++;
+      }
+      const float Sx = get(S, kx);
+      // length precision guard: rebase once the bound on this segment's
+      // length exceeds 2^-10 of the leaf edge (w base cells)
+      need64 = need64 || (get(eb, kx) + e_ent > 0x1p-10f * (float)w);
+      float len = (Sx - s_ent) * ldexpf(1.0f, (int)dep - (int)db);
+      len = len > 0.0f ? len : 0.0f;
+      // composite; every visited leaf is recorded: for a ray outside the face
+      // band the exact segment is positive even when it rounds to 0 here
+      const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * len * -1.4426950408889634f);
+      const float a = T - Tn;
+      C.x = __builtin_fmaf(a, (float)(pay.x & 0xffu), C.x);
+      C.y = __builtin_fmaf(a, (float)((pay.x >> 8) & 0xffu), C.y);
+      C.z = __builtin_fmaf(a, (float)((pay.x >> 16) & 0xffu), C.z);
+      T = Tn;
+      if (TRACE) record(sk, n_rec, I, len);
+      ++n_rec;
+      // ---- neighbour across the exit face
+      const uint32_t ck = get(c, kx);
+      const bool upk = get(up, kx);
+      const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
+      if (mv.at_edge || mv.N == CVX_NONE || (use_stop && 1.0f - T >= v.alpha_stop)) {
+        if (!mv.at_edge && mv.N == CVX_NONE) out.flags |= CVX_RAYFLAG_BAD_LINK;
+        break;
+      }
+      if (STATS) acc.outer += mv.outer;
+      I = mv.N;
+      r = ld_rec(rec, I);
+      pay = ld_pay(payp, I);
+      set(c, kx, mv.nc);
+      for (int k = 0; k < 3; ++k) set(Nk, k, get(Nk, k) + (k == kx ? (int32_t)w : 0));
+      s_ent = Sx;
+      e_ent = get(eb, kx);
+      ke = kx;
+      // a coarser leaf: its far planes lie an integer number of cells further
+      const uint32_t dL = (r.x & 1u) ? ((r.x >> 1) & 63u) : dep;
+      const uint32_t m = dL < dep ? dep - dL : 0u;
+      const uint32_t mask = (1u << m) - 1u;
+      const uint32_t lw = db - dep;  // w = 2^lw
+      for (int k = 0; k < 3; ++k) {
+        const uint32_t lo = get(c, k) & mask;
+        set(Nk, k, get(Nk, k) + (int32_t)((get(up, k) ? mask - lo : lo) << lw));
+        set(c, k, get(c, k) >> m);
+      }
+      w <<= m;
+      dep -= m;
+    }
+    if (need64) {
+      // FP64 rebase at the near face (axis ke) of the current cell
+      const int kr = ke < 0 ? 0 : ke;
+      const uint32_t cr = get(c, kr);
+      const double Xp = (double)(get(up, kr) ? cr : cr + 1u) * ldexp(1.0, -(int)dep);
+      const double te = (Xp - get(o, kr)) * get(inv, kr);
+      for (int k = 0; k < 3; ++k) set(q, k, k == kr ? Xp : get(o, k) + te * get(d, k));
+      rebase(te);
+    }
+  }
+  const float k255 = 1.0f / 255.0f;
+  out.rgba[0] = C.x * k255;
+  out.rgba[1] = C.y * k255;
+  out.rgba[2] = C.z * k255;
+  out.rgba[3] = 1.0f - T;
+  out.n = n_rec;
+  if (STATS) acc.leaves += n_rec;
+}
+
+// ----------------------------------------------------------------------------
+// FP64_PLAIN: canvas-global FP64; exit parameters from the exact face planes
+// ((integer + side) 2^-dep - o_k) / d_k every step, FP64 compositing.
+// ----------------------------------------------------------------------------
+template <bool TRACE, bool STATS>
+__device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
+                          Sink sk, Acc& acc, Out& out) {
+  const V3<double> o{v.o[0], v.o[1], v.o[2]};
+  const double Rd = (double)v.R;
+  const void* rec = v.rec;
+  const bool use_stop = v.alpha_stop < 1.0f;
+  V3<double> inv;
+  for (int k = 0; k < 3; ++k) set(inv, k, 1.0 / get(d, k));
+  V3<double> q;
+  for (int k = 0; k < 3; ++k) {
+    double qk = get(o, k) + en.t0 * get(d, k);
+    if (k == en.kin) qk = en.side ? Rd : 0.0;
+    set(q, k, qk < 0.0 ? 0.0 : (qk > Rd ? Rd : qk));
+  }
+  uint32_t I, dep = 0;
+  V3<uint32_t> c;
   root_of<double>(q, up, v.R, c, I);
   uint4 r = ld_rec(rec, I);
   descend<double>(rec, q, up, I, dep, c, r);
   if (STATS) acc.descent += dep;
-
-  // ---------------------------------------------------------------- FP64 plain
-  if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
-    double T = 1.0, C[3] = {0.0, 0.0, 0.0};
-    double t_ent = en.t0;
-    for (uint32_t step = 0;; ++step) {
-      if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
-      double h = ldexp(1.0, -(int)dep);
-      double best = __builtin_inf();
-      int kx = 0;
-      for (int k = 0; k < 3; ++k) {
-        if (d[k] == 0.0) continue;
-        double X = (double)(c[k] + (up[k] ? 1u : 0u)) * h;
-        double tt = (X - o[k]) * inv[k];
-        if (tt < best) { best = tt; kx = k; }
-      }
-      double len = ldexp(best - t_ent, (int)dep);
-      len = len > 0.0 ? len : 0.0;
-      {
-        double col[3], kap;
-        if (v.fmt == CVX_LEAF_F64) {
-          double4 p = ((const double4*)v.pay)[I];
-          col[0] = p.x; col[1] = p.y; col[2] = p.z; kap = p.w;
-        } else {
-          uint2 p = ((const uint2*)v.pay)[I];
-          col[0] = (double)(p.x & 0xffu) / 255.0;
-          col[1] = (double)((p.x >> 8) & 0xffu) / 255.0;
-          col[2] = (double)((p.x >> 16) & 0xffu) / 255.0;
-          kap = (double)(float)__builtin_bit_cast(_Float16, (unsigned short)(p.y & 0xffffu));
-        }
-        double Tn = T * exp(-kap * len);
-        double a = T - Tn;
-        for (int k = 0; k < 3; ++k) C[k] = __builtin_fma(a, col[k], C[k]);
-        T = Tn;
-        if (TRACE && n_rec < sk.cap) { sk.ids[n_rec] = I; if (sk.len32) sk.len32[n_rec] = (float)len; if (sk.len64) sk.len64[n_rec] = len; }
-        ++n_rec;
-        if (use_stop && 1.0 - T >= (double)v.alpha_stop) break;
-      }
-      const uint32_t ck = pick(c, kx);
-      const bool upk = pick(up, kx);
-      const uint32_t side_n = v.R << dep;
-      if (upk ? (ck + 1u >= side_n) : (ck == 0u)) break;
-      const uint32_t nc = upk ? ck + 1u : ck - 1u;
-      uint32_t N;
-      bool outer;
-      if (dep == 0) {
-        uint32_t stride = kx == 0 ? 1u : (kx == 1 ? v.R : v.R * v.R);
-        N = upk ? I + stride : I - stride;
-        outer = true;
-      } else if ((ck & 1u) == (upk ? 0u : 1u)) {
-        N = upk ? I + (1u << kx) : I - (1u << kx);
-        outer = false;
-      } else {
-        N = kx == 0 ? r.y : (kx == 1 ? r.z : r.w);
-        outer = true;
-      }
-      if (N == CVX_NONE) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
-      if (STATS) acc.outer += outer;
-      double X = (double)(upk ? nc : ck) * h;
-      put(c, kx, nc);
-      I = N;
-      r = ld_rec(rec, N);
-      if (r.x & 1u) {
-        uint32_t dN = (r.x >> 1) & 63u;
-        if (dN < dep) {
-          for (int k = 0; k < 3; ++k) c[k] >>= (dep - dN);
-          dep = dN;
-        }
-      } else {
-        for (int k = 0; k < 3; ++k) q[k] = o[k] + best * d[k];
-        put(q, kx, X);
-        uint32_t d0 = dep;
-        descend<double>(rec, q, up, I, dep, c, r);
-        if (STATS) acc.descent += dep - d0;
-      }
-      t_ent = best > t_ent ? best : t_ent;
-    }
-    out.rgba[0] = C[0];
-    out.rgba[1] = C[1];
-    out.rgba[2] = C[2];
-    out.rgba[3] = 1.0 - T;
-    out.n = n_rec;
-    if (STATS) acc.leaves += n_rec;
-    return;
-  }
-
-  // ------------------------------------------------------------- FP32 rebased
-  if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
-    float df[3], idf[3];
-    bool par[3];
+  double T = 1.0;
+  V3<double> C{0.0, 0.0, 0.0};
+  double t_ent = en.t0;
+  uint32_t n_rec = 0;
+  for (uint32_t step = 0;; ++step) {
+    if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    const double h = ldexp(1.0, -(int)dep);
+    double best = __builtin_inf();
+    int kx = 0;
     for (int k = 0; k < 3; ++k) {
-      par[k] = !(__builtin_fabs(d[k]) >= 0x1p-60);
-      df[k] = (float)d[k];
-      idf[k] = par[k] ? 0.0f : 1.0f / df[k];
+      const double X = (double)(get(c, k) + (get(up, k) ? 1u : 0u)) * h;
+      const double tt = get(d, k) == 0.0 ? __builtin_inf() : (X - get(o, k)) * get(inv, k);
+      kx = tt < best ? k : kx;
+      best = tt < best ? tt : best;
     }
-    // bound on |t| + |q| along the ray, for the rebase error bound
-    const float tR = (float)(en.t1 + Rd + 1.0);
-    float p[3];
-    for (int k = 0; k < 3; ++k) p[k] = (float)((ldexp(q[k], (int)dep) - (double)c[k]) - 0.5);
-    float ep = ldexpf(tR, (int)dep - 50) + 0x1p-24f;
-    float T = 1.0f, C[3] = {0.f, 0.f, 0.f};
-    uint2 pay = ((const uint2*)v.pay)[I];
-    for (uint32_t step = 0;; ++step) {
-      if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
-      // exit face in cell-local FP32, with error bounds
-      float tk[3], ek[3];
-      for (int k = 0; k < 3; ++k) {
-        if (par[k]) {
-          tk[k] = BIGF;
-          ek[k] = 0.0f;
-        } else {
-          float f = up[k] ? 0.5f : -0.5f;
-          tk[k] = (f - p[k]) * idf[k];
-          ek[k] = (ep + 0x1p-24f) * __builtin_fabsf(idf[k]) * 1.0001f +
-                  0x1.81p-23f * __builtin_fabsf(tk[k]);
-        }
-      }
-      int kx = tk[1] < tk[0] ? 1 : 0;
-      if (tk[2] < pick(tk, kx)) kx = 2;
-      const float tmin = pick(tk, kx), emin = pick(ek, kx);
-      bool cert = true;
-      for (int k = 0; k < 3; ++k) {
-        float m = tk[k] - tmin;
-        float need = (ek[k] + emin) * 1.0625f + 0x1p-22f * __builtin_fabsf(tk[k]);
-        if (k != kx && !(m > need)) cert = false;
-      }
-      float len = tmin;
-      float ekx = emin;
-      bool force = false;
-      if (!cert) {
-        // FP64 decision from the exact face planes
-        double h = ldexp(1.0, -(int)dep);
-        double best = __builtin_inf();
-        int kb = kx;
-        for (int k = 0; k < 3; ++k) {
-          if (d[k] == 0.0) continue;
-          double X = (double)(c[k] + (up[k] ? 1u : 0u)) * h;
-          double tt = (X - o[k]) * inv[k];
-          if (tt < best) { best = tt; kb = k; }
-        }
-        if (pick(tk, kb) < BIGF) {
-          len = pick(tk, kb);
-          ekx = pick(ek, kb);
-        }
-        kx = kb;
-        force = true;
-        out.flags |= CVX_RAYFLAG_FP64_EXIT;
-        if (STATS) acc.fp64_exit++;
-      }
-      len = len > 0.0f ? len : 0.0f;
-      // every visited leaf is recorded: for a ray not within the face band of
-      // a visited leaf the exact segment is positive even when it rounds to 0
-      {
-        float col[3], kap;
-        decode8(pay, col, kap);
-        float Tn = T * __expf(-kap * len);
-        float a = T - Tn;
-        for (int k = 0; k < 3; ++k) C[k] = __builtin_fma(a, col[k], C[k]);
-        T = Tn;
-        if (TRACE && n_rec < sk.cap) { sk.ids[n_rec] = I; if (sk.len32) sk.len32[n_rec] = len; if (sk.len64) sk.len64[n_rec] = len; }
-        ++n_rec;
-        if (use_stop && 1.0f - T >= v.alpha_stop) break;
-      }
-      const uint32_t ck = pick(c, kx);
-      const bool upk = pick(up, kx);
-      const uint32_t side_n = v.R << dep;
-      if (upk ? (ck + 1u >= side_n) : (ck == 0u)) break;
-      const uint32_t nc = upk ? ck + 1u : ck - 1u;
-      uint32_t N;
-      bool outer;
-      if (dep == 0) {
-        uint32_t stride = kx == 0 ? 1u : (kx == 1 ? v.R : v.R * v.R);
-        N = upk ? I + stride : I - stride;
-        outer = true;
-      } else if ((ck & 1u) == (upk ? 0u : 1u)) {
-        N = upk ? I + (1u << kx) : I - (1u << kx);
-        outer = false;
-      } else {
-        N = kx == 0 ? r.y : (kx == 1 ? r.z : r.w);
-        outer = true;
-      }
-      if (N == CVX_NONE) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
-      if (STATS) acc.outer += outer;
-      uint4 rN = ld_rec(rec, N);
-      uint2 payN = ((const uint2*)v.pay)[N];
-      put(c, kx, nc);
-      const bool leafN = rN.x & 1u;
-      const uint32_t dN = leafN ? ((rN.x >> 1) & 63u) : dep;
-      if (!leafN || force || ep > EP_MAX) {
-        // FP64 rebase at the exactly known crossing plane
-        double h = ldexp(1.0, -(int)dep);
-        double X = (double)(upk ? nc : ck) * h;
-        double tp = (X - pick(o, kx)) * pick(inv, kx);
-        for (int k = 0; k < 3; ++k) q[k] = o[k] + tp * d[k];
-        put(q, kx, X);
-        if (dN < dep) {
-          for (int k = 0; k < 3; ++k) c[k] >>= (dep - dN);
-          dep = dN;
-        }
-        I = N;
-        r = rN;
-        if (!leafN) {
-          uint32_t d0 = dep;
-          descend<double>(rec, q, up, I, dep, c, r);
-          payN = ((const uint2*)v.pay)[I];
-          if (STATS) acc.descent += dep - d0;
-        }
-        for (int k = 0; k < 3; ++k)
-          p[k] = (float)((ldexp(q[k], (int)dep) - (double)c[k]) - 0.5);
-        ep = ldexpf(tR, (int)dep - 50) + 0x1p-24f;
-        if (STATS) acc.rebase++;
-      } else {
-        // move to the exit point in the same-depth frame of the neighbour
-        for (int k = 0; k < 3; ++k)
-          p[k] = k == kx ? (upk ? -0.5f : 0.5f) : __builtin_fmaf(len, df[k], p[k]);
-        ep = ep + ekx + len * 0x1p-23f + 0x1p-25f;
-        if (dN < dep) {
-          const uint32_t m = dep - dN;
-          const float sc = ldexpf(1.0f, -(int)m);
-          const uint32_t mask = (1u << m) - 1u;
-          for (int k = 0; k < 3; ++k) {
-            p[k] = ((float)(c[k] & mask) + (p[k] + 0.5f)) * sc - 0.5f;
-            c[k] >>= m;
-          }
-          dep = dN;
-          ep = ep * sc + 0x1p-23f;
-        }
-        I = N;
-        r = rN;
-      }
-      pay = payN;
+    double len = ldexp(best - t_ent, (int)dep);
+    len = len > 0.0 ? len : 0.0;
+    double cr, cg, cb, kap;
+    if (v.fmt == CVX_LEAF_F64) {
+      const double4 p = ((const double4*)v.pay)[I];
+      cr = p.x; cg = p.y; cb = p.z; kap = p.w;
+    } else {
+      const uint2 p = ((const uint2*)v.pay)[I];
+      cr = (double)(p.x & 0xffu) / 255.0;
+      cg = (double)((p.x >> 8) & 0xffu) / 255.0;
+      cb = (double)((p.x >> 16) & 0xffu) / 255.0;
+      kap = (double)kappa_of(p);
     }
-    out.rgba[0] = C[0];
-    out.rgba[1] = C[1];
-    out.rgba[2] = C[2];
-    out.rgba[3] = 1.0f - T;
-    out.n = n_rec;
-    if (STATS) acc.leaves += n_rec;
+    const double Tn = T * exp(-kap * len);
+    const double a = T - Tn;
+    C.x = __builtin_fma(a, cr, C.x);
+    C.y = __builtin_fma(a, cg, C.y);
+    C.z = __builtin_fma(a, cb, C.z);
+    T = Tn;
+    if (TRACE) record(sk, n_rec, I, len);
+    ++n_rec;
+    const uint32_t ck = get(c, kx);
+    const bool upk = get(up, kx);
+    const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
+    if (mv.at_edge || mv.N == CVX_NONE || (use_stop && 1.0 - T >= (double)v.alpha_stop)) {
+      if (!mv.at_edge && mv.N == CVX_NONE) out.flags |= CVX_RAYFLAG_BAD_LINK;
+      break;
+    }
+    if (STATS) acc.outer += mv.outer;
+    const double X = (double)(upk ? mv.nc : ck) * h;
+    set(c, kx, mv.nc);
+    I = mv.N;
+    r = ld_rec(rec, I);
+    if (r.x & 1u) {
+      const uint32_t dL = (r.x >> 1) & 63u;
+      const uint32_t m = dL < dep ? dep - dL : 0u;
+      for (int k = 0; k < 3; ++k) set(c, k, get(c, k) >> m);
+      dep -= m;
+    } else {
+      for (int k = 0; k < 3; ++k) set(q, k, k == kx ? X : get(o, k) + best * get(d, k));
+      const uint32_t d0 = dep;
+      descend<double>(rec, q, up, I, dep, c, r);
+      if (STATS) acc.descent += dep - d0;
+    }
+    t_ent = best > t_ent ? best : t_ent;
+  }
+  out.rgba[0] = C.x;
+  out.rgba[1] = C.y;
+  out.rgba[2] = C.z;
+  out.rgba[3] = 1.0 - T;
+  out.n = n_rec;
+  if (STATS) acc.leaves += n_rec;
+}
+
+// ----------------------------------------------------------------------------
+// FP32_NAIVE: canvas-global FP32 planes and points (drifts at depth).
+// ----------------------------------------------------------------------------
+template <bool TRACE, bool STATS>
+__device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
+                           Sink sk, Acc& acc, Out& out) {
+  const void* rec = v.rec;
+  const void* payp = v.pay;
+  const bool use_stop = v.alpha_stop < 1.0f;
+  V3<float> of, df, idf;
+  for (int k = 0; k < 3; ++k) {
+    set(of, k, (float)v.o[k]);
+    set(df, k, (float)get(d, k));
+    set(idf, k, get(df, k) == 0.0f ? 0.0f : 1.0f / get(df, k));
+  }
+  float t_ent = (float)en.t0;
+  V3<float> q;
+  for (int k = 0; k < 3; ++k)
+    set(q, k, k == en.kin ? (en.side ? (float)v.R : 0.0f) : get(of, k) + t_ent * get(df, k));
+  uint32_t I, dep = 0;
+  V3<uint32_t> c;
+  root_of<float>(q, up, v.R, c, I);
+  uint4 r = ld_rec(rec, I);
+  descend<float>(rec, q, up, I, dep, c, r);
+  if (STATS) acc.descent += dep;
+  float T = 1.0f;
+  V3<float> C{0.f, 0.f, 0.f};
+  uint32_t n_rec = 0;
+  for (uint32_t step = 0;; ++step) {
+    if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    const float h = ldexpf(1.0f, -(int)dep);
+    float best = BIGF, Xb = 0.0f;
+    int kx = 0;
+    for (int k = 0; k < 3; ++k) {
+      const float X = (float)(get(c, k) + (get(up, k) ? 1u : 0u)) * h;
+      const float tt = get(df, k) == 0.0f ? BIGF : (X - get(of, k)) * get(idf, k);
+      kx = tt < best ? k : kx;
+      Xb = tt < best ? X : Xb;
+      best = tt < best ? tt : best;
+    }
+    float len = (best - t_ent) * ldexpf(1.0f, (int)dep);
+    len = len > 0.0f ? len : 0.0f;
+    const uint2 pay = ld_pay(payp, I);
+    const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * len * -1.4426950408889634f);
+    const float a = T - Tn;
+    C.x = __builtin_fmaf(a, (float)(pay.x & 0xffu), C.x);
+    C.y = __builtin_fmaf(a, (float)((pay.x >> 8) & 0xffu), C.y);
+    C.z = __builtin_fmaf(a, (float)((pay.x >> 16) & 0xffu), C.z);
+    T = Tn;
+    if (TRACE) record(sk, n_rec, I, len);
+    ++n_rec;
+    const uint32_t ck = get(c, kx);
+    const bool upk = get(up, kx);
+    const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
+    if (mv.at_edge || mv.N == CVX_NONE || (use_stop && 1.0f - T >= v.alpha_stop)) {
+      if (!mv.at_edge && mv.N == CVX_NONE) out.flags |= CVX_RAYFLAG_BAD_LINK;
+      break;
+    }
+    if (STATS) acc.outer += mv.outer;
+    set(c, kx, mv.nc);
+    I = mv.N;
+    r = ld_rec(rec, I);
+    if (r.x & 1u) {
+      const uint32_t dL = (r.x >> 1) & 63u;
+      const uint32_t m = dL < dep ? dep - dL : 0u;
+      for (int k = 0; k < 3; ++k) set(c, k, get(c, k) >> m);
+      dep -= m;
+    } else {
+      for (int k = 0; k < 3; ++k) set(q, k, k == kx ? Xb : get(of, k) + best * get(df, k));
+      const uint32_t d0 = dep;
+      descend<float>(rec, q, up, I, dep, c, r);
+      if (STATS) acc.descent += dep - d0;
+    }
+    t_ent = best > t_ent ? best : t_ent;
+  }
+  const float k255 = 1.0f / 255.0f;
+  out.rgba[0] = C.x * k255;
+  out.rgba[1] = C.y * k255;
+  out.rgba[2] = C.z * k255;
+  out.rgba[3] = 1.0f - T;
+  out.n = n_rec;
+  if (STATS) acc.leaves += n_rec;
+}
+
+template <int VAR, bool TRACE, bool STATS>
+__device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out) {
+  const V3<double> d = ray_dir(v, px, py);
+  const V3<double> o{v.o[0], v.o[1], v.o[2]};
+  out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
+  out.flags = 0;
+  out.n = 0;
+  if (STATS) acc.rays++;
+  const Entry en = canvas_entry(o, d, (double)v.R);
+  if (!en.hit) return;
+  const V3<bool> up{d.x > 0.0, d.y > 0.0, d.z > 0.0};
+  if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
+    cast_fp32<TRACE, STATS>(v, d, en, up, sk, acc, out);
+  } else if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
+    cast_fp64<TRACE, STATS>(v, d, en, up, sk, acc, out);
+  } else {
+    cast_naive<TRACE, STATS>(v, d, en, up, sk, acc, out);
   }
 }
 
@@ -548,13 +659,13 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
         if (a.views[mid].first_tile <= (uint64_t)w) lo = mid; else hi = mid - 1;
       }
       const DView& v = a.views[lo];
-      uint64_t t = (uint64_t)w - v.first_tile;
-      uint32_t tx = (uint32_t)(t % v.tiles_x), ty = (uint32_t)(t / v.tiles_x);
-      uint32_t x = tx * a.tile_w + lane % a.tile_w, y = ty * a.tile_h + lane / a.tile_w;
+      const uint64_t t = (uint64_t)w - v.first_tile;
+      const uint32_t tx = (uint32_t)(t % v.tiles_x), ty = (uint32_t)(t / v.tiles_x);
+      const uint32_t x = tx * a.tile_w + lane % a.tile_w, y = ty * a.tile_h + lane / a.tile_w;
       if (x < v.W && y < v.H) {
         Sink sk{nullptr, nullptr, nullptr, 0};
         cast_ray<VAR, false, STATS>(v, x, y, sk, acc, res);
-        uint64_t pix = v.out_off + (uint64_t)y * v.W + x;
+        const uint64_t pix = v.out_off + (uint64_t)y * v.W + x;
         if constexpr (OUT64) {
           double2* o2 = (double2*)a.out + 2 * pix;
           o2[0] = make_double2(res.rgba[0], res.rgba[1]);
@@ -565,10 +676,10 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
         }
       }
     } else {
-      uint64_t ri = (uint64_t)w * 64u + lane;
+      const uint64_t ri = (uint64_t)w * 64u + lane;
       if (ri < a.hdr->n_rays) {
-        uint64_t id = a.ray_ids[ri];
-        uint32_t vi = (uint32_t)(id >> 32), pix = (uint32_t)(id & 0xffffffffu);
+        const uint64_t id = a.ray_ids[ri];
+        const uint32_t vi = (uint32_t)(id >> 32), pix = (uint32_t)(id & 0xffffffffu);
         a.n_leaves[ri] = 0;
         a.flags[ri] = CVX_RAYFLAG_BAD_LINK;
         if (vi < nv) {
@@ -588,7 +699,7 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
     }
   }
   if constexpr (STATS) {
-    uint32_t vals[6] = {acc.rays, acc.leaves, acc.outer, acc.descent, acc.fp64_exit, acc.rebase};
+    const uint32_t vals[6] = {acc.rays, acc.leaves, acc.outer, acc.descent, acc.fp64_exit, acc.rebase};
     for (int s = 0; s < 6; ++s) {
       uint32_t x = vals[s];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
