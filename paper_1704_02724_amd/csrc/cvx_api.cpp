@@ -369,6 +369,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     first += (uint64_t)dv.tiles_x * tiles_y;
     uint64_t cap = 3ull * c.desc.R * (1ull << std::min<uint32_t>(c.depth, 40)) + 16;
     dv.max_steps = (uint32_t)std::min<uint64_t>(cap, 1ull << 22);
+    dv.n_nodes = (uint32_t)c.n_nodes;
   }
   CastHeader& H = *ctx->h_hdr;
   H.total_work = tr ? (tr->n + 63) / 64 : first;

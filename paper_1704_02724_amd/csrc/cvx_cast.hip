@@ -146,11 +146,14 @@ __device__ __forceinline__ uint2 ld_pay(const void* pay, uint32_t i) {
 }
 
 // Descend from the current cell (r refined) to the leaf containing q; on a
-// mid-plane the child on the side the ray moves into is taken.
+// mid-plane the child on the side the ray moves into is taken.  Returns false
+// (and stops) if a child index falls outside the pool.
 template <class Real>
-__device__ __forceinline__ void descend(const void* rec, const V3<Real>& q, const V3<bool>& up,
-                                        uint32_t& I, uint32_t& dep, V3<uint32_t>& c, uint4& r) {
+__device__ __forceinline__ bool descend(const void* rec, uint32_t n_nodes, const V3<Real>& q,
+                                        const V3<bool>& up, uint32_t& I, uint32_t& dep,
+                                        V3<uint32_t>& c, uint4& r) {
   while (!(r.x & 1u)) {
+    if (r.x >= n_nodes - 7u) return false;
     const Real h = (Real)ldexp(1.0, -(int)dep);
     uint32_t oct = 0;
     for (int k = 0; k < 3; ++k) {
@@ -164,6 +167,7 @@ __device__ __forceinline__ void descend(const void* rec, const V3<Real>& q, cons
     ++dep;
     r = ld_rec(rec, I);
   }
+  return true;
 }
 
 // Root cell containing q (ties go to the side the ray moves into).
@@ -280,9 +284,10 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
   float s_ent = 0.0f, e_ent = 0.0f, beta = 0.0f;
   // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
   // current cell I is descended first when it is refined.
+  bool bad = false;  // a node index outside the pool (never for a validated pool)
   auto rebase = [&](double te) __attribute__((always_inline)) {
     const uint32_t d0 = dep;
-    descend<double>(rec, q, up, I, dep, c, r);
+    bad = bad || !descend<double>(rec, v.n_nodes, q, up, I, dep, c, r);
     if (STATS) acc.descent += dep - d0;
     pay = ld_pay(payp, I);
     db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
@@ -305,37 +310,45 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
   V3<float> C{0.f, 0.f, 0.f};
   uint32_t n_rec = 0;
   int ke = en.kin;  // axis of the face the current cell was entered through
+  // per-ray integer constants of the travel direction
+  const V3<uint32_t> upm{up.x ? ~0u : 0u, up.y ? ~0u : 0u, up.z ? ~0u : 0u};
+  const V3<int32_t> sgn{up.x ? 1 : -1, up.y ? 1 : -1, up.z ? 1 : -1};
+  uint32_t rstride[3] = {1u, v.R, v.R * v.R};
   for (uint32_t step = 0;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
+    // s-values of the far planes (leaf) or of the mid-planes (refined cell)
+    // and their error bounds; a refined cell's mid-plane lies half a cell
+    // before its far plane
+    const bool leaf = r.x & 1u;
+    const uint32_t half = w >> 1;
+    const int32_t off = leaf ? 0 : (int32_t)half;
+    const float betac = beta * BETA_C;
+    V3<float> S, eb;
+    for (int k = 0; k < 3; ++k) {
+      const float Nf = (float)(get(Nk, k) - off);
+      set(S, k, __builtin_fmaf(Nf, get(tD, k), get(S0, k)));
+      set(eb, k, __builtin_fmaf(ALPHA_C, __builtin_fmaf(__builtin_fabsf(Nf), get(tD, k), get(S0, k)),
+                                betac));
+    }
     bool need64 = false;
-    if (!(r.x & 1u)) {
+    if (!leaf) {
       // ---- refined cell entered through its near face on axis ke: one level
       need64 = w < 2u || ke < 0 || anypar;
-      const uint32_t half = w >> 1;
+      if (r.x >= v.n_nodes - 7u) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
       uint32_t oct = 0;
-      V3<uint32_t> b3;
-      V3<int32_t> dN;
       for (int k = 0; k < 3; ++k) {
-        const float Nm = (float)(get(Nk, k) - (int32_t)half);
-        const float M = __builtin_fmaf(Nm, get(tD, k), get(S0, k));
-        const float eM = __builtin_fmaf(
-            ALPHA, __builtin_fmaf(__builtin_fabsf(Nm), get(tD, k), get(S0, k)), beta);
-        const float diff = s_ent - M;
+        const float diff = s_ent - get(S, k);
         const bool isk = k == ke;
         const bool far = !isk && diff >= 0.0f;
-        const bool sure = __builtin_fabsf(diff) > (e_ent + eM) * 1.0625f +
-                                                      0x1p-23f * __builtin_fmaxf(__builtin_fabsf(M), s_ent);
+        const bool sure = __builtin_fabsf(diff) > e_ent + get(eb, k);
         need64 = need64 || (!isk && !sure);
         const uint32_t b = (get(up, k) == far) ? 1u : 0u;
-        set(b3, k, b);
-        set(dN, k, far ? 0 : (int32_t)half);
         oct |= b << k;
+        set(Nk, k, get(Nk, k) - (far ? 0 : (int32_t)half));
+        set(c, k, 2u * get(c, k) + b);
       }
       if (!need64) {
-        for (int k = 0; k < 3; ++k) {
-          set(Nk, k, get(Nk, k) - get(dN, k));
-          set(c, k, 2u * get(c, k) + get(b3, k));
-        }
         I = r.x + oct;
         ++dep;
         w = half;
@@ -344,16 +357,15 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
         if (STATS) acc.descent++;
         continue;
       }
+      // undo the speculative update; the FP64 rebase descends from here
+      for (int k = 0; k < 3; ++k) {
+        const uint32_t ck = get(c, k);
+        const bool far = ((ck & 1u) != 0u) == get(up, k);
+        set(Nk, k, get(Nk, k) + (far ? 0 : (int32_t)half));
+        set(c, k, ck >> 1);
+      }
     } else {
       // ---- leaf: exit face, certified against the error bounds
-      V3<float> S, eb;
-      const float betac = beta * BETA_C;
-      for (int k = 0; k < 3; ++k) {
-        const float Nf = (float)get(Nk, k);
-        set(S, k, __builtin_fmaf(Nf, get(tD, k), get(S0, k)));
-        set(eb, k, __builtin_fmaf(ALPHA_C, __builtin_fmaf(__builtin_fabsf(Nf), get(tD, k), get(S0, k)),
-                                  betac));
-      }
       const float Smin = __builtin_fminf(S.x, __builtin_fminf(S.y, S.z));
       int kx = 2;
       kx = S.y == Smin ? 1 : kx;
@@ -378,9 +390,10 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
         if (STATS) acc.fp64_exit++;
       }
       const float Sx = get(S, kx);
+      const float ex = get(eb, kx);
       // length precision guard: rebase once the bound on this segment's
       // length exceeds 2^-10 of the leaf edge (w base cells)
-      need64 = need64 || (get(eb, kx) + e_ent > 0x1p-10f * (float)w);
+      need64 = need64 || (ex + e_ent > 0x1p-10f * (float)w);
       float len = (Sx - s_ent) * ldexpf(1.0f, (int)dep - (int)db);
       len = len > 0.0f ? len : 0.0f;
       // composite; every visited leaf is recorded: for a ray outside the face
@@ -393,32 +406,48 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
       T = Tn;
       if (TRACE) record(sk, n_rec, I, len);
       ++n_rec;
-      // ---- neighbour across the exit face
+      // ---- neighbour across the exit face: sibling, next root or G_3 link
       const uint32_t ck = get(c, kx);
-      const bool upk = get(up, kx);
-      const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
-      if (mv.at_edge || mv.N == CVX_NONE || (use_stop && 1.0f - T >= v.alpha_stop)) {
-        if (!mv.at_edge && mv.N == CVX_NONE) out.flags |= CVX_RAYFLAG_BAD_LINK;
+      const int32_t sk_ = get(sgn, kx);
+      const uint32_t nc = ck + (uint32_t)sk_;           // wraps to ~0 below 0
+      const bool at_edge = nc >= (v.R << dep);
+      const bool root = dep == 0;
+      // the sibling lies across the face when the cell is even going up
+      // (odd going down): (ck ^ upm) & 1 == 1 in both cases
+      const bool inner = !root && (((ck ^ get(upm, kx)) & 1u) == 1u);
+      uint32_t rs = rstride[0];
+      rs = kx == 1 ? rstride[1] : rs;
+      rs = kx == 2 ? rstride[2] : rs;
+      const uint32_t sib = I + (uint32_t)(sk_ * (int32_t)(root ? rs : (1u << kx)));
+      uint32_t link = r.y;
+      link = kx == 1 ? r.z : link;
+      link = kx == 2 ? r.w : link;
+      const uint32_t Nn = (root || inner) ? sib : link;
+      // a null link (CVX_NONE) is also >= n_nodes
+      if (at_edge || Nn >= v.n_nodes || (use_stop && 1.0f - T >= v.alpha_stop)) {
+        if (!at_edge && Nn >= v.n_nodes) out.flags |= CVX_RAYFLAG_BAD_LINK;
         break;
       }
-      if (STATS) acc.outer += mv.outer;
-      I = mv.N;
+      if (STATS) acc.outer += !inner;
+      I = Nn;
       r = ld_rec(rec, I);
       pay = ld_pay(payp, I);
-      set(c, kx, mv.nc);
-      for (int k = 0; k < 3; ++k) set(Nk, k, get(Nk, k) + (k == kx ? (int32_t)w : 0));
+      set(c, kx, nc);
       s_ent = Sx;
-      e_ent = get(eb, kx);
+      e_ent = ex;
       ke = kx;
-      // a coarser leaf: its far planes lie an integer number of cells further
+      // far planes move by one cell on the exit axis, and for a coarser
+      // leaf by the integer number of cells to its far planes:
+      // (mask - lo) = lo ^ mask going up, lo going down
       const uint32_t dL = (r.x & 1u) ? ((r.x >> 1) & 63u) : dep;
       const uint32_t m = dL < dep ? dep - dL : 0u;
       const uint32_t mask = (1u << m) - 1u;
       const uint32_t lw = db - dep;  // w = 2^lw
       for (int k = 0; k < 3; ++k) {
-        const uint32_t lo = get(c, k) & mask;
-        set(Nk, k, get(Nk, k) + (int32_t)((get(up, k) ? mask - lo : lo) << lw));
-        set(c, k, get(c, k) >> m);
+        const uint32_t ckk = get(c, k);
+        const uint32_t dist = (ckk ^ get(upm, k)) & mask;
+        set(Nk, k, get(Nk, k) + (int32_t)(((k == kx ? 1u : 0u) + dist) << lw));
+        set(c, k, ckk >> m);
       }
       w <<= m;
       dep -= m;
@@ -465,7 +494,7 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
   V3<uint32_t> c;
   root_of<double>(q, up, v.R, c, I);
   uint4 r = ld_rec(rec, I);
-  descend<double>(rec, q, up, I, dep, c, r);
+  bool bad = !descend<double>(rec, v.n_nodes, q, up, I, dep, c, r);
   if (STATS) acc.descent += dep;
   double T = 1.0;
   V3<double> C{0.0, 0.0, 0.0};
@@ -473,6 +502,7 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
   uint32_t n_rec = 0;
   for (uint32_t step = 0;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
     const double h = ldexp(1.0, -(int)dep);
     double best = __builtin_inf();
     int kx = 0;
@@ -506,8 +536,8 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
     const uint32_t ck = get(c, kx);
     const bool upk = get(up, kx);
     const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
-    if (mv.at_edge || mv.N == CVX_NONE || (use_stop && 1.0 - T >= (double)v.alpha_stop)) {
-      if (!mv.at_edge && mv.N == CVX_NONE) out.flags |= CVX_RAYFLAG_BAD_LINK;
+    if (mv.at_edge || mv.N >= v.n_nodes || (use_stop && 1.0 - T >= (double)v.alpha_stop)) {
+      if (!mv.at_edge && mv.N >= v.n_nodes) out.flags |= CVX_RAYFLAG_BAD_LINK;
       break;
     }
     if (STATS) acc.outer += mv.outer;
@@ -523,7 +553,7 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
     } else {
       for (int k = 0; k < 3; ++k) set(q, k, k == kx ? X : get(o, k) + best * get(d, k));
       const uint32_t d0 = dep;
-      descend<double>(rec, q, up, I, dep, c, r);
+      bad = !descend<double>(rec, v.n_nodes, q, up, I, dep, c, r);
       if (STATS) acc.descent += dep - d0;
     }
     t_ent = best > t_ent ? best : t_ent;
@@ -559,13 +589,14 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
   V3<uint32_t> c;
   root_of<float>(q, up, v.R, c, I);
   uint4 r = ld_rec(rec, I);
-  descend<float>(rec, q, up, I, dep, c, r);
+  bool bad = !descend<float>(rec, v.n_nodes, q, up, I, dep, c, r);
   if (STATS) acc.descent += dep;
   float T = 1.0f;
   V3<float> C{0.f, 0.f, 0.f};
   uint32_t n_rec = 0;
   for (uint32_t step = 0;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
     const float h = ldexpf(1.0f, -(int)dep);
     float best = BIGF, Xb = 0.0f;
     int kx = 0;
@@ -590,8 +621,8 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
     const uint32_t ck = get(c, kx);
     const bool upk = get(up, kx);
     const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
-    if (mv.at_edge || mv.N == CVX_NONE || (use_stop && 1.0f - T >= v.alpha_stop)) {
-      if (!mv.at_edge && mv.N == CVX_NONE) out.flags |= CVX_RAYFLAG_BAD_LINK;
+    if (mv.at_edge || mv.N >= v.n_nodes || (use_stop && 1.0f - T >= v.alpha_stop)) {
+      if (!mv.at_edge && mv.N >= v.n_nodes) out.flags |= CVX_RAYFLAG_BAD_LINK;
       break;
     }
     if (STATS) acc.outer += mv.outer;
@@ -606,7 +637,7 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
     } else {
       for (int k = 0; k < 3; ++k) set(q, k, k == kx ? Xb : get(of, k) + best * get(df, k));
       const uint32_t d0 = dep;
-      descend<float>(rec, q, up, I, dep, c, r);
+      bad = !descend<float>(rec, v.n_nodes, q, up, I, dep, c, r);
       if (STATS) acc.descent += dep - d0;
     }
     t_ent = best > t_ent ? best : t_ent;

@@ -54,6 +54,8 @@ struct DView {
   uint64_t first_tile;  // prefix sum of tile counts over the views
   float alpha_stop;
   uint32_t max_steps;
+  uint32_t n_nodes;     // node ids at or above this are never loaded
+  uint32_t pad;
 };
 
 // Launch-invariant header in device memory, so a captured graph can be
