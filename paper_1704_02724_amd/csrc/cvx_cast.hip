@@ -213,6 +213,16 @@ __device__ __forceinline__ Move neighbour(const DView& v, uint32_t I, const uint
   return m;
 }
 
+// An empty asm the compiler must assume rewrites x.  Loads and arithmetic
+// that depend on the result cannot be hoisted out of the loop holding it, so
+// the rare FP64 paths re-read their loop-invariant inputs (eye, view basis)
+// there instead of pinning them in registers for the whole traversal.
+template <class T>
+__device__ __forceinline__ T opaque(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 __device__ __forceinline__ float kappa_of(uint2 p) {
   return (float)__builtin_bit_cast(_Float16, (unsigned short)(p.y & 0xffffu));
 }
@@ -247,18 +257,37 @@ constexpr float ALPHA_C = 0x1p-21f * 1.0625f + 0x1p-23f;
 constexpr float BETA_C = 1.0625f;
 constexpr uint32_t DB_MARGIN = 8;
 
+// Per-lane LDS slot holding the FP64 eye and direction of the lane's ray,
+// [6][blockDim.x] doubles (component-major, so lanes read consecutive words).
+// The FP32 traversal needs them only on its rare FP64 paths; keeping them here
+// instead of in 12 VGPRs raises the number of resident wavefronts.
+extern __shared__ double s_ray[];
+
+typedef __attribute__((address_space(3))) double lds_f64;
+
+struct RaySlot {
+  lds_f64* p;  // this lane's first component
+  uint32_t stride;
+  __device__ __forceinline__ void put(const V3<double>& o, const V3<double>& d) const {
+    p[0] = o.x; p[stride] = o.y; p[2 * stride] = o.z;
+    p[3 * stride] = d.x; p[4 * stride] = d.y; p[5 * stride] = d.z;
+  }
+  // component j (0-2 eye, 3-5 direction), read through an opaque pointer so
+  // the load stays on the rare path that needs it
+  __device__ __forceinline__ double at(int j) const { return opaque(p)[j * stride]; }
+};
+
 template <bool TRACE, bool STATS>
-__device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
-                          Sink sk, Acc& acc, Out& out) {
-  const V3<double> o{v.o[0], v.o[1], v.o[2]};
+__device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& o,
+                          const V3<double>& d, const Entry& en, const V3<bool>& up, Sink sk,
+                          Acc& acc, Out& out) {
   const double Rd = (double)v.R;
   const void* rec = v.rec;
   const void* payp = v.pay;
-  V3<double> inv;
+  slot.put(o, d);
   V3<float> tD;
   for (int k = 0; k < 3; ++k) {
     const double dk = get(d, k);
-    set(inv, k, 1.0 / dk);
     set(tD, k, __builtin_fabs(dk) >= 0x1p-60 ? 1.0f / __builtin_fabsf((float)dk) : 0.0f);
   }
   const bool anypar = tD.x == 0.0f || tD.y == 0.0f || tD.z == 0.0f;
@@ -293,9 +322,11 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
     db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
     w = 1u << (db - dep);
     const double hd = ldexp(1.0, -(int)dep);
+    // rolled: one FP64 division live at a time
+#pragma unroll 1
     for (int k = 0; k < 3; ++k) {
-      const double X = (double)(get(c, k) + (get(up, k) ? 1u : 0u)) * hd;
-      const double Tk = (X - get(o, k)) * get(inv, k);
+      const double X = (double)get(c, k) * hd + (get(up, k) ? hd : 0.0);  // exact
+      const double Tk = (X - slot.at(k)) / slot.at(3 + k);
       set(S0, k, get(tD, k) == 0.0f ? BIGF : (float)ldexp(Tk - te, (int)db));
     }
     Nk = V3<int32_t>{0, 0, 0};
@@ -310,9 +341,6 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
   V3<float> C{0.f, 0.f, 0.f};
   uint32_t n_rec = 0;
   int ke = en.kin;  // axis of the face the current cell was entered through
-  // per-ray integer constants of the travel direction
-  const V3<uint32_t> upm{up.x ? ~0u : 0u, up.y ? ~0u : 0u, up.z ? ~0u : 0u};
-  const V3<int32_t> sgn{up.x ? 1 : -1, up.y ? 1 : -1, up.z ? 1 : -1};
   uint32_t rstride[3] = {1u, v.R, v.R * v.R};
   for (uint32_t step = 0;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
@@ -378,9 +406,11 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
         const double hd = ldexp(1.0, -(int)dep);
         double best = __builtin_inf();
         int kb = kx;
+#pragma unroll 1
         for (int k = 0; k < 3; ++k) {
-          const double X = (double)(get(c, k) + (get(up, k) ? 1u : 0u)) * hd;
-          const double tt = get(d, k) == 0.0 ? __builtin_inf() : (X - get(o, k)) * get(inv, k);
+          const double X = (double)get(c, k) * hd + (get(up, k) ? hd : 0.0);
+          const double dk = slot.at(3 + k);
+          const double tt = dk == 0.0 ? __builtin_inf() : (X - slot.at(k)) / dk;
           kb = tt < best ? k : kb;
           best = tt < best ? tt : best;
         }
@@ -408,13 +438,14 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
       ++n_rec;
       // ---- neighbour across the exit face: sibling, next root or G_3 link
       const uint32_t ck = get(c, kx);
-      const int32_t sk_ = get(sgn, kx);
+      const bool upk = get(up, kx);
+      const int32_t sk_ = upk ? 1 : -1;
       const uint32_t nc = ck + (uint32_t)sk_;           // wraps to ~0 below 0
       const bool at_edge = nc >= (v.R << dep);
       const bool root = dep == 0;
       // the sibling lies across the face when the cell is even going up
-      // (odd going down): (ck ^ upm) & 1 == 1 in both cases
-      const bool inner = !root && (((ck ^ get(upm, kx)) & 1u) == 1u);
+      // (odd going down)
+      const bool inner = !root && (((ck & 1u) == 0u) == upk);
       uint32_t rs = rstride[0];
       rs = kx == 1 ? rstride[1] : rs;
       rs = kx == 2 ? rstride[2] : rs;
@@ -445,7 +476,7 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
       const uint32_t lw = db - dep;  // w = 2^lw
       for (int k = 0; k < 3; ++k) {
         const uint32_t ckk = get(c, k);
-        const uint32_t dist = (ckk ^ get(upm, k)) & mask;
+        const uint32_t dist = get(up, k) ? (~ckk & mask) : (ckk & mask);
         set(Nk, k, get(Nk, k) + (int32_t)(((k == kx ? 1u : 0u) + dist) << lw));
         set(c, k, ckk >> m);
       }
@@ -457,8 +488,8 @@ __device__ void cast_fp32(const DView& v, const V3<double>& d, const Entry& en, 
       const int kr = ke < 0 ? 0 : ke;
       const uint32_t cr = get(c, kr);
       const double Xp = (double)(get(up, kr) ? cr : cr + 1u) * ldexp(1.0, -(int)dep);
-      const double te = (Xp - get(o, kr)) * get(inv, kr);
-      for (int k = 0; k < 3; ++k) set(q, k, k == kr ? Xp : get(o, k) + te * get(d, k));
+      const double te = (Xp - slot.at(kr)) / slot.at(3 + kr);
+      for (int k = 0; k < 3; ++k) set(q, k, k == kr ? Xp : slot.at(k) + te * slot.at(3 + k));
       rebase(te);
     }
   }
@@ -653,6 +684,7 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
 
 template <int VAR, bool TRACE, bool STATS>
 __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out) {
+  const RaySlot slot{(lds_f64*)(s_ray + threadIdx.x), blockDim.x};
   const V3<double> d = ray_dir(v, px, py);
   const V3<double> o{v.o[0], v.o[1], v.o[2]};
   out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
@@ -663,12 +695,25 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   if (!en.hit) return;
   const V3<bool> up{d.x > 0.0, d.y > 0.0, d.z > 0.0};
   if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
-    cast_fp32<TRACE, STATS>(v, d, en, up, sk, acc, out);
+    cast_fp32<TRACE, STATS>(v, slot, o, d, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
     cast_fp64<TRACE, STATS>(v, d, en, up, sk, acc, out);
   } else {
     cast_naive<TRACE, STATS>(v, d, en, up, sk, acc, out);
   }
+}
+
+// Copy of a view that is the same in every lane (render mode: a tile never
+// straddles views), read into scalar registers, so the pool pointers and
+// sizes do not occupy vector registers during the traversal.
+__device__ __forceinline__ DView uniform_view(const DView& v) {
+  constexpr int n = sizeof(DView) / 4;
+  uint32_t w[n];
+  __builtin_memcpy(w, &v, sizeof(DView));
+  for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  DView u;
+  __builtin_memcpy(&u, w, sizeof(DView));
+  return u;
 }
 
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
@@ -680,7 +725,9 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
   for (;;) {
     uint32_t w = 0;
     if (lane == 0) w = atomicAdd(&a.hdr->queue, 1u);
-    w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
+    // every lane is active here (the loop exit is uniform), so the first
+    // active lane is lane 0
+    w = __builtin_amdgcn_readfirstlane(w);
     if ((uint64_t)w >= total) break;
     Out res;
     if constexpr (!TRACE) {
@@ -689,7 +736,7 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
         int mid = (lo + hi + 1) >> 1;
         if (a.views[mid].first_tile <= (uint64_t)w) lo = mid; else hi = mid - 1;
       }
-      const DView& v = a.views[lo];
+      const DView v = uniform_view(a.views[lo]);
       const uint64_t t = (uint64_t)w - v.first_tile;
       const uint32_t tx = (uint32_t)(t % v.tiles_x), ty = (uint32_t)(t / v.tiles_x);
       const uint32_t x = tx * a.tile_w + lane % a.tile_w, y = ty * a.tile_h + lane / a.tile_w;
@@ -745,7 +792,8 @@ __global__ void k_reset(CastHeader* hdr) {
 
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
 int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
-  hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), 0,
+  const size_t lds = VAR == (int)CVX_VARIANT_FP32_REBASED ? 6u * sizeof(double) * wg_size : 0u;
+  hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                      (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
