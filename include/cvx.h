@@ -74,7 +74,7 @@ typedef struct {
   double origin[3];
   double root_edge;     /* > 0 */
   uint32_t R;           /* roots per axis, 1..64 */
-  uint32_t max_depth;   /* deepest level present, <= CVX_MAX_DEPTH; R * 2^max_depth <= 2^31 */
+  uint32_t max_depth;   /* deepest level present, <= CVX_MAX_DEPTH; R * 2^max_depth <= 2^30 */
   uint32_t leaf_format; /* CVX_LEAF_* */
   uint32_t reserved;    /* must be 0 */
 } cvx_canvas_desc;

@@ -37,8 +37,10 @@ int check_desc(const cvx_canvas_desc* d, std::string& msg) {
     msg = "max_depth exceeds CVX_MAX_DEPTH";
     return CVX_ERR_INVALID_ARG;
   }
-  if ((uint64_t)d->R << d->max_depth > (1ull << 31)) {
-    msg = "R * 2^max_depth must not exceed 2^31";
+  // cell coordinates at the deepest level, and the FP32 traversal's signed
+  // plane offsets (at most R * 2^max_depth base cells), stay in int32 range
+  if ((uint64_t)d->R << d->max_depth > (1ull << 30)) {
+    msg = "R * 2^max_depth must not exceed 2^30";
     return CVX_ERR_INVALID_ARG;
   }
   return CVX_OK;

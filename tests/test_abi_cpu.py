@@ -78,7 +78,8 @@ def test_depth_limit_and_desc_checks(cvx):
     rc, msg = cvx.cvx_validate_pool(_desc(cvx, cv, max_depth=real_depth - 1), cv.nodes, cv.leaves)
     assert rc == cvx.CVX_ERR_BAD_POOL and "depth" in msg
     for over in (dict(R=0), dict(max_depth=31), dict(root_edge=0.0), dict(leaf_format=2),
-                 dict(root_edge=float("nan")), dict(R=4, max_depth=30)):
+                 dict(root_edge=float("nan")), dict(R=4, max_depth=30),
+                 dict(R=2, max_depth=30)):
         rc, msg = cvx.cvx_validate_pool(_desc(cvx, cv, **over), cv.nodes, cv.leaves)
         assert rc == cvx.CVX_ERR_INVALID_ARG, (over, rc, msg)
 
