@@ -109,6 +109,22 @@ def time_variant(sess, views, variant, steps, warmup, tuning):
     return out, wall, per
 
 
+def time_per_view(sess, views, variant, steps, tuning):
+    """The same views rendered with one cvx_render (one persistent launch) per
+    view, each a replayed graph; returns wall seconds per step."""
+    torch = sess.torch
+    out = torch.empty((sess.out_pixels(views), 4), dtype=torch.float32, device=sess.device)
+    for v in views:
+        sess.render([v], variant, out=out, use_graph=True, **tuning)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for v in views:
+            sess.render([v], variant, out=out, use_graph=True, **tuning)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +140,12 @@ def main():
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--wg-size", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use --tile/--workgroups/--wg-size instead of cvx_autotune's pick")
+    ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--per-view-steps", type=int, default=-1,
+                    help="steps of the one-launch-per-view comparison (default 3 when the "
+                         "workload has more than two views; 0 skips it)")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the device-to-device copy timed as the measured HBM peak "
                          "(also the reference for hardware byte counters); 0 skips it")
@@ -174,6 +196,18 @@ def main():
             f"{copy_bps / 1e9:.1f} GB/s")
         del src, dst
 
+    tuning64 = dict(tuning)
+    tune_rows = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        tuning, tune_rows = sess.autotune(views, args.variant, reps=args.tune_reps)
+        log(f"autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; fastest: "
+            + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}: {r[4]:.3f}ms"
+                        for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
+        if args.fp64_steps > 0:
+            tuning64, _ = sess.autotune(views, "fp64_plain", reps=max(1, args.tune_reps - 2))
+            log(f"autotune fp64_plain: {tuning64}")
+
     # --- timed: production variant
     out, wall, per = time_variant(sess, views, args.variant, args.steps, args.warmup, tuning)
     ms_step = wall * 1e3 / args.steps
@@ -193,9 +227,21 @@ def main():
     # --- FP64 plain baseline on the same GPU
     fp64 = None
     if args.fp64_steps > 0:
-        _, wall64, per64 = time_variant(sess, views, "fp64_plain", args.fp64_steps, 1, tuning)
+        _, wall64, per64 = time_variant(sess, views, "fp64_plain", args.fp64_steps, 1, tuning64)
         fp64 = rays / (wall64 / args.fp64_steps) / 1e6
         log(f"fp64_plain: {wall64 * 1e3 / args.fp64_steps:.3f} ms/step, {fp64:.1f} Mrays/s")
+
+    # --- one launch per view, for the batching comparison
+    per_view = None
+    pv_steps = args.per_view_steps if args.per_view_steps >= 0 else (3 if len(views) > 2 else 0)
+    if pv_steps > 0:
+        pv_s, pv_out = time_per_view(sess, views, args.variant, pv_steps, tuning)
+        same = bool(torch.equal(pv_out, out))
+        per_view = dict(mrays=round(rays / pv_s / 1e6, 2), ms_per_step=round(pv_s * 1e3, 3),
+                        launches_per_step=len(views), steps=pv_steps,
+                        batched_speedup=round(pv_s / (ms_step * 1e-3), 3), same_image=same)
+        log(f"per-view launches: {per_view}")
+        del pv_out
 
     # --- parity on a seeded sample (sequences + RGBA) against the oracle
     ids = sample_ids(views, args.parity_sample, 12345)
@@ -253,7 +299,10 @@ def main():
             "rays_per_step": int(rays),
             "nodes": int(sum(c.n_nodes for c in cv)),
             "variant": args.variant,
-            "tile": args.tile,
+            "tile": "%dx%d" % tuple(tuning["tile"]) if tuning["tile"][0] else args.tile,
+            "workgroups": int(tuning["workgroups"]),
+            "wg_size": int(tuning["wg_size"]),
+            "autotuned": not args.no_autotune,
             "graph": True,
         },
         "roofline": {
@@ -274,6 +323,7 @@ def main():
         },
         "fp64_plain_mrays": round(fp64, 2) if fp64 else None,
         "speedup_vs_fp64_plain": round(value / fp64, 3) if fp64 else None,
+        "per_view_launches": per_view,
         "parity": parity,
         "kernel_stats": {k: int(v) for k, v in zip(
             ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase"], s[:6])},

@@ -177,6 +177,30 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
 int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
                const cvx_render_opts* opts);
 
+/* One candidate launch shape timed by cvx_autotune. */
+typedef struct {
+  uint32_t tile_w, tile_h; /* pixel tile, tile_w * tile_h = 64 */
+  uint32_t wg_size;        /* threads per workgroup */
+  uint32_t workgroups;     /* persistent grid size */
+  float ms;                /* mean time of one render, milliseconds */
+  uint32_t reserved;
+} cvx_tune_result;
+
+/* Autotuner of the batch scheduler's launch shape: renders `views` exactly as
+ * cvx_render would with base's variant and use_graph, once per candidate
+ * tile shape (8x8, 16x4, 4x16, 32x2), workgroup size (64, 128, 256) and
+ * persistent grid (16, 28, 32, 64 wavefronts per CU), one untimed warm-up
+ * then `reps` renders timed with HIP events on the context stream.  Writes
+ * base with the fastest shape filled in to *best and, when results is not
+ * NULL, up to max_results timed candidates in the order tried (the count
+ * tried goes to *n_results when not NULL).  out_dev receives the renders
+ * (identical for every candidate).  base->trace and base->stats must be
+ * NULL; reps in [1, 1000].  Synchronous; an error from a candidate's render
+ * is returned as is. */
+int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+                 const cvx_render_opts* base, uint32_t reps, cvx_render_opts* best,
+                 cvx_tune_result* results, uint32_t max_results, uint32_t* n_results);
+
 /* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
 int cvx_free_pool(cvx_ctx* ctx, int canvas_id);
 

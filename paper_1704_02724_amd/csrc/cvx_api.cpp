@@ -442,4 +442,82 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   return CVX_OK;
 }
 
+int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+                 const cvx_render_opts* base, uint32_t reps, cvx_render_opts* best,
+                 cvx_tune_result* results, uint32_t max_results, uint32_t* n_results) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!best) return fail(ctx, CVX_ERR_INVALID_ARG, "best is NULL");
+  if (reps < 1 || reps > 1000) return fail(ctx, CVX_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  if (results == nullptr && max_results != 0)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "results is NULL but max_results > 0");
+  cvx_render_opts b{};
+  if (base) b = *base;
+  if (b.trace || b.stats)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "autotune times plain renders: no trace, no stats");
+  static const uint32_t kTiles[][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}};
+  static const uint32_t kWg[] = {64, 128, 256};
+  static const uint32_t kWavesPerCu[] = {16, 28, 32, 64};
+  CVX_HIP(hipSetDevice(ctx->device));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CVX_HIP(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(ctx, he, "hipEventCreate");
+  }
+  int rc = CVX_OK;
+  float best_ms = 0.0f;
+  bool have = false;
+  uint32_t count = 0;
+  for (const auto& t : kTiles) {
+    for (uint32_t wg : kWg) {
+      for (uint32_t wpc : kWavesPerCu) {
+        if (rc != CVX_OK) break;
+        cvx_render_opts o = b;
+        o.tile_w = t[0];
+        o.tile_h = t[1];
+        o.wg_size = wg;
+        o.workgroups = (uint32_t)ctx->n_cu * wpc * 64u / wg;
+        rc = cvx_render(ctx, views, n_views, out_dev, &o);  // warm-up, captures the graph
+        if (rc != CVX_OK) break;
+        if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess) {
+          rc = hip_fail(ctx, he, "hipEventRecord");
+          break;
+        }
+        for (uint32_t r = 0; r < reps && rc == CVX_OK; ++r)
+          rc = cvx_render(ctx, views, n_views, out_dev, &o);
+        if (rc != CVX_OK) break;
+        float ms = 0.0f;
+        if ((he = hipEventRecord(e1, ctx->stream)) != hipSuccess ||
+            (he = hipEventSynchronize(e1)) != hipSuccess ||
+            (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+          rc = hip_fail(ctx, he, "timing a candidate");
+          break;
+        }
+        ms /= (float)reps;
+        if (count < max_results) {
+          cvx_tune_result& x = results[count];
+          x.tile_w = o.tile_w;
+          x.tile_h = o.tile_h;
+          x.wg_size = o.wg_size;
+          x.workgroups = o.workgroups;
+          x.ms = ms;
+          x.reserved = 0;
+        }
+        ++count;
+        if (!have || ms < best_ms) {
+          have = true;
+          best_ms = ms;
+          *best = o;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (n_results) *n_results = count;
+  return rc;
+}
+
 }  // extern "C"

@@ -43,7 +43,7 @@ CVX_STAT_COUNT = 8
 
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",
             "cvx_last_error", "cvx_status_str", "cvx_validate_pool", "cvx_validate_views",
-            "cvx_pool_bytes"]
+            "cvx_pool_bytes", "cvx_autotune"]
 
 
 class cvx_canvas_desc(ctypes.Structure):
@@ -76,6 +76,12 @@ class cvx_render_opts(ctypes.Structure):
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
+class cvx_tune_result(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_uint32), ("tile_h", ctypes.c_uint32),
+                ("wg_size", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+
+
 class CvxError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{status_name(code)}: {msg}")
@@ -102,6 +108,10 @@ _lib.cvx_validate_pool.argtypes = [ctypes.POINTER(cvx_canvas_desc), _vp, ctypes.
 _lib.cvx_validate_views.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_char_p,
                                     ctypes.c_size_t]
 _lib.cvx_pool_bytes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+_lib.cvx_autotune.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(cvx_render_opts),
+                              ctypes.c_uint32, ctypes.POINTER(cvx_render_opts),
+                              ctypes.POINTER(cvx_tune_result), ctypes.c_uint32,
+                              ctypes.POINTER(ctypes.c_uint32)]
 
 
 def library():
@@ -166,6 +176,20 @@ def cvx_render(ctx, views, out_ptr, opts=None):
     o = opts if opts is not None else cvx_render_opts()
     _check(ctx, _lib.cvx_render(ctx, ctypes.cast(views, _vp), len(views), _vp(int(out_ptr)),
                                 ctypes.byref(o)))
+
+
+def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=64):
+    """Returns (best cvx_render_opts, list of (tile_w, tile_h, wg_size, workgroups, ms))."""
+    b = base if base is not None else cvx_render_opts()
+    best = cvx_render_opts()
+    res = (cvx_tune_result * max_results)()
+    n = ctypes.c_uint32()
+    _check(ctx, _lib.cvx_autotune(ctx, ctypes.cast(views, _vp), len(views), _vp(int(out_ptr)),
+                                  ctypes.byref(b), int(reps), ctypes.byref(best), res,
+                                  int(max_results), ctypes.byref(n)))
+    rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms))
+            for r in res[:min(n.value, max_results)]]
+    return best, rows
 
 
 def cvx_free_pool(ctx, canvas_id):

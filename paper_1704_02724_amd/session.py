@@ -76,6 +76,22 @@ class Session:
         self._leave(out, *([stats] if stats is not None else []))
         return out
 
+    def autotune(self, views, variant="fp32_rebased", out=None, reps=3, use_graph=True):
+        """Times every candidate launch shape (cvx_autotune); returns the fastest as
+        render keyword arguments, and the table of (tile_w, tile_h, wg_size,
+        workgroups, ms) rows."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.out_pixels(views), 4), dtype=torch.float32, device=self.device)
+        varr = cvx.make_views(views)
+        base = cvx.make_opts(variant, use_graph=use_graph)
+        self._enter()
+        best, rows = cvx.cvx_autotune(self.ctx, varr, out.data_ptr(), base, reps)
+        self._leave(out)
+        tuning = dict(tile=(best.tile_w, best.tile_h), workgroups=best.workgroups,
+                      wg_size=best.wg_size)
+        return tuning, rows
+
     def new_stats(self):
         return self.torch.zeros(cvx.CVX_STAT_COUNT, dtype=self.torch.int64, device=self.device)
 

@@ -241,3 +241,28 @@ def test_error_paths(sess):
     with pytest.raises(cvx.CvxError) as e:
         sess.free(6)
     assert e.value.code == cvx.CVX_ERR_NOT_FOUND
+
+
+def test_autotune_picks_a_timed_shape_and_keeps_the_image(sess):
+    """cvx_autotune times every candidate launch shape; every candidate renders
+    the same image, and the one it returns is the fastest it timed."""
+    from paper_1704_02724_amd import cvx
+    w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=96, H=80)
+    sess.upload(0, w.canvases[0])
+    ref = sess.render(w.views, "fp32_rebased").cpu().numpy()
+    out = sess.torch.full((96 * 80, 4), -1.0, dtype=sess.torch.float32, device=sess.device)
+    tuning, rows = sess.autotune(w.views, "fp32_rebased", out=out, reps=2)
+    sess.torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    assert len(rows) == 4 * 3 * 4
+    assert {(r[0], r[1]) for r in rows} == {(8, 8), (16, 4), (4, 16), (32, 2)}
+    assert all(r[4] > 0.0 for r in rows)
+    best = min(rows, key=lambda r: r[4])
+    assert tuning == dict(tile=(best[0], best[1]), workgroups=best[3], wg_size=best[2])
+    img = sess.render(w.views, "fp32_rebased", use_graph=True, **tuning)
+    np.testing.assert_array_equal(img.cpu().numpy(), ref)
+    varr = cvx.make_views(w.views)
+    for reps, base in ((0, None), (2, cvx.make_opts("fp32_rebased", stats_ptr=sess.new_stats().data_ptr()))):
+        with pytest.raises(cvx.CvxError) as e:
+            cvx.cvx_autotune(sess.ctx, varr, out.data_ptr(), base, reps)
+        assert e.value.code == cvx.CVX_ERR_INVALID_ARG

@@ -89,3 +89,37 @@ def test_depth30_naive_fails_visibly(sess, depth30):
     cmp, err, orc, _ = _sampled(sess, depth30, ids, "fp32_naive")
     print(f"depth30 naive: mismatch {cmp['seq_mismatch']} of {cmp['n']}, rgba err {err:.3g}")
     assert cmp["seq_mismatch"] > 0
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return configs.batch()
+
+
+def test_batch_sampled(sess, batch):
+    """Eight canvases (depth 16..28) and 64 views of uneven size in one
+    persistent launch; the sample spans every view."""
+    ids = sample_ray_ids(batch.views, 32768, 4004)
+    vi = (ids >> np.uint64(32)).astype(np.int64)
+    assert len(np.unique(vi)) == len(batch.views)
+    cmp, err, orc, _ = _sampled(sess, batch, ids, "fp32_rebased")
+    print(f"batch: {cmp['n']} rays over {len(batch.views)} views, flagged {cmp['flagged']}, "
+          f"mismatch {cmp['seq_mismatch']}, rgba err {err:.3g}, "
+          f"mean leaves {orc['n_leaves'].mean():.1f}")
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= 1e-3
+
+
+def test_large_recipe_reduced_sampled(sess):
+    """The large canvas recipe (radius 2^-24..2^-2, depth 26, stop at alpha
+    0.99) with 2,000 strokes and 512x512 eyes: rays stop early; the oracle
+    flags rays whose alpha ends within 1e-5 of the stop value."""
+    w = configs.large(n_strokes=2000, W=512, H=512)
+    ids = sample_ray_ids(w.views, 32768, 5005)
+    cmp, err, orc, _ = _sampled(sess, w, ids, "fp32_rebased")
+    stopped = int((orc["rgba"][:, 3] >= 0.99).sum())
+    print(f"large (reduced): {cmp['n']} rays, stopped {stopped}, flagged {cmp['flagged']}, "
+          f"mismatch {cmp['seq_mismatch']}, rgba err {err:.3g}")
+    assert stopped > 0
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= 1e-3
