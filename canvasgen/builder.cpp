@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -205,6 +206,9 @@ void emit_leaf(Result& res, uint64_t li, const T* c, int fmt) {
   }
 }
 
+// Progress lines on stderr for long builds (set by cg_set_verbose).
+std::atomic<int> g_verbose{0};
+
 template <class T>
 int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Strokes& st, int fmt,
           Result& res) {
@@ -289,7 +293,9 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
     for (size_t i = 0; i < nsub; ++i) order[i] = i;
     std::sort(order.begin(), order.end(),
               [&](size_t a, size_t b) { return lists[a].size() > lists[b].size(); });
-    std::atomic<size_t> next{0};
+    std::atomic<size_t> next{0}, done{0};
+    if (g_verbose)
+      std::fprintf(stderr, "[canvasgen] top tree built, painting %zu subtrees\n", nsub);
     auto work = [&]() {
       for (;;) {
         size_t w = next.fetch_add(1);
@@ -305,6 +311,9 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
           for (int64_t j = st.off[s]; j < st.off[s + 1]; ++j)
             B.apply_stamp(P, 0, (int)B.S, sd.ix, sd.iy, sd.iz, s, st.stamps[j], 0xffffffffu,
                           [](uint32_t) {});
+        const size_t d = done.fetch_add(1) + 1;
+        if (g_verbose && nsub >= 10 && d % (nsub / 10) == 0)
+          std::fprintf(stderr, "[canvasgen] painted %zu / %zu subtrees\n", d, nsub);
       }
     };
     int nt = std::max(1, nthreads);
@@ -314,6 +323,7 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
     for (auto& t : th) t.join();
   }
 
+  if (g_verbose) std::fprintf(stderr, "[canvasgen] emitting the pool\n");
   // Emit in depth-first group order.  Count first.
   uint64_t nn = P0, nl = 0;
   {
@@ -422,6 +432,9 @@ void cg_result_copy(void* h, uint32_t* nodes, void* leaves, uint64_t* depth_hist
 }
 
 void cg_result_free(void* h) { delete (Result*)h; }
+
+// Nonzero: long builds print progress lines on stderr.
+void cg_set_verbose(int v) { g_verbose = v; }
 
 uint16_t cg_f32_to_f16(float f) { return f32_to_f16(f); }
 

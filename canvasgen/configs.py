@@ -20,8 +20,10 @@ cameras.
             on canvas v mod 8, pairs (2j, 2j+1) are stereo pairs with a square
             side uniform in [256, 2160].  Pair j looks at canvas j mod 8 (a
             stereo pair shares one canvas), so each canvas gets 4 pairs.
-  large     100,000 strokes r in 2^[-24,-2], D=26, k=4; stereo 2160x2160 per eye,
-            rays stop once accumulated alpha reaches 0.99.
+  large     55,000 strokes r in 2^[-24,-2], D=26, k=4 (about 1.5 G nodes: the
+            pool grows by about 26.9 K nodes per stroke, so 100,000 strokes
+            would pass the 2^31 node ids of the pool format); stereo
+            2160x2160 per eye, rays stop once accumulated alpha reaches 0.99.
 """
 from __future__ import annotations
 
@@ -114,10 +116,15 @@ def batch(seed=4000, leaf_format=LEAF_RGBA8_F16, threads=0, side_scale=1.0):
     return Workload("batch", canvases, views, strokes, dict(seed=seed, depths=BATCH_DEPTHS))
 
 
-def large(seed=5, leaf_format=LEAF_RGBA8_F16, threads=0, W=2160, H=2160, n_strokes=100000):
+LARGE_STROKES = 55000
+
+
+def large(seed=5, leaf_format=LEAF_RGBA8_F16, threads=0, W=2160, H=2160,
+          n_strokes=LARGE_STROKES):
     rng = _rng(seed)
     st = gen_strokes(rng, n_strokes, -24.0, -2.0)
-    cv = build_from_strokes(st, 1, 26, 4.0, leaf_format, split_depth=5, threads=threads)
+    cv = build_from_strokes(st, 1, 26, 4.0, leaf_format, split_depth=5, threads=threads,
+                            verbose=n_strokes >= 10000)
     eye, fwd, r = eye_near_stroke(rng, st, 2.0 ** -16)
     views = stereo_pair(eye, fwd, 0.5 * r, 1.0, W, H, alpha_stop=0.99)
     return Workload("large", [cv], views, [st], dict(seed=seed, D=26))

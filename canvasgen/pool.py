@@ -86,6 +86,8 @@ def _load():
                                         ctypes.POINTER(u32)]
         lib.cg_result_copy.argtypes = [vp, vp, vp, vp]
         lib.cg_result_free.argtypes = [vp]
+        lib.cg_set_verbose.argtypes = [i32]
+        lib.cg_set_verbose.restype = None
         lib.cg_f32_to_f16.argtypes = [ctypes.c_float]
         lib.cg_f32_to_f16.restype = ctypes.c_uint16
         _lib = lib
@@ -97,9 +99,11 @@ def f32_to_f16_bits(x: float) -> int:
 
 
 def build_from_strokes(strokes, R: int, max_depth: int, k: float, leaf_format: int,
-                       split_depth: int = 0, threads: int = 0) -> Canvas:
-    """Refine and paint the canvas stroke by stroke (Sec. 5.1-5.2), emit the pool."""
+                       split_depth: int = 0, threads: int = 0, verbose: bool = False) -> Canvas:
+    """Refine and paint the canvas stroke by stroke (Sec. 5.1-5.2), emit the pool.
+    verbose: the builder prints progress lines on stderr (long builds)."""
     lib = _load()
+    lib.cg_set_verbose(1 if verbose else 0)
     if threads <= 0:
         threads = min(16, os.cpu_count() or 1)
     h = ctypes.c_void_p()
