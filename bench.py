@@ -202,7 +202,7 @@ def main():
         t = time.perf_counter()
         tuning, tune_rows = sess.autotune(views, args.variant, reps=args.tune_reps)
         log(f"autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; fastest: "
-            + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}: {r[4]:.3f}ms"
+            + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}: {r[4]:.3f}ms"
                         for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
         if args.fp64_steps > 0:
             tuning64, _ = sess.autotune(views, "fp64_plain", reps=max(1, args.tune_reps - 2))
@@ -302,6 +302,7 @@ def main():
             "tile": "%dx%d" % tuple(tuning["tile"]) if tuning["tile"][0] else args.tile,
             "workgroups": int(tuning["workgroups"]),
             "wg_size": int(tuning["wg_size"]),
+            "top_lookup": int(tuning.get("top_lookup", 0)),
             "autotuned": not args.no_autotune,
             "graph": True,
         },
@@ -325,8 +326,9 @@ def main():
         "speedup_vs_fp64_plain": round(value / fp64, 3) if fp64 else None,
         "per_view_launches": per_view,
         "parity": parity,
-        "kernel_stats": {k: int(v) for k, v in zip(
-            ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase"], s[:6])},
+        "kernel_stats": dict({k: int(v) for k, v in zip(
+            ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase", "steps", "slots"], s[:8])},
+            lane_occupancy=round(float(s[6] / s[7]), 4) if s[7] else None),
         "cpu_baseline": cpu,
     }
     sess.close()

@@ -138,7 +138,8 @@ typedef struct {
   uint32_t wg_size;     /* threads per workgroup: 64, 128 or 256 */
   uint32_t use_graph;   /* 1: capture the launch in a HIP graph and replay it */
   uint32_t out_f64;     /* FP64_PLAIN only: out is double RGBA instead of float */
-  uint32_t reserved;
+  uint32_t top_lookup;  /* 0: ray starts are located through the pool's top-level table;
+                           1: they descend from the root array (same result) */
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;
@@ -149,6 +150,8 @@ typedef struct {
 #define CVX_STAT_DESCENT 3     /* tree levels descended (first leaf depth + depth increases) */
 #define CVX_STAT_FP64_EXIT 4   /* exit decisions taken by the FP64 fallback */
 #define CVX_STAT_REBASE 5      /* FP64 rebases of the cell-local point */
+#define CVX_STAT_STEPS 6       /* traversal loop iterations, summed over rays */
+#define CVX_STAT_SLOTS 7       /* lane slots: per 64-ray tile, 64 x its longest ray's iterations */
 #define CVX_STAT_COUNT 8
 
 /* Create a context on HIP device `hip_device` that enqueues on `hip_stream`
@@ -162,7 +165,9 @@ int cvx_create(cvx_ctx** ctx, int hip_device, void* hip_stream);
  * leaf indices < n_leaves, finite non-negative kappa), re-laid out on the
  * device into 16-byte node records plus a node-indexed payload array, and
  * the three outer-face neighbour links per node are built on the GPU level
- * by level.  Replaces any pool under canvas_id only on success.  Returns
+ * by level.  A top-level table (for every cell of depth L <= 6, at most 2^18
+ * cells, the node of depth <= L covering it) is built on the GPU too; ray
+ * starts use it to skip the first L levels of their descent.  Replaces any pool under canvas_id only on success.  Returns
  * CVX_ERR_BAD_POOL for an invalid pool, CVX_ERR_OOM when the device lacks
  * room (checked before any allocation). Synchronous. */
 int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
@@ -183,13 +188,14 @@ typedef struct {
   uint32_t wg_size;        /* threads per workgroup */
   uint32_t workgroups;     /* persistent grid size */
   float ms;                /* mean time of one render, milliseconds */
-  uint32_t reserved;
+  uint32_t top_lookup;     /* as in cvx_render_opts */
 } cvx_tune_result;
 
 /* Autotuner of the batch scheduler's launch shape: renders `views` exactly as
  * cvx_render would with base's variant and use_graph, once per candidate
- * tile shape (8x8, 16x4, 4x16, 32x2), workgroup size (64, 128, 256) and
- * persistent grid (16, 28, 32, 64 wavefronts per CU), one untimed warm-up
+ * tile shape (8x8, 16x4, 4x16, 32x2), workgroup size (64, 128, 256),
+ * persistent grid (16, 28, 32, 64 wavefronts per CU) and top-level lookup
+ * (on, off), one untimed warm-up
  * then `reps` renders timed with HIP events on the context stream.  Writes
  * base with the fastest shape filled in to *best and, when results is not
  * NULL, up to max_results timed candidates in the order tried (the count

@@ -67,6 +67,7 @@ int hip_fail(cvx_ctx* ctx, hipError_t e, const char* where) {
 void free_canvas(DevCanvas& c) {
   if (c.rec) (void)hipFree(c.rec);
   if (c.pay) (void)hipFree(c.pay);
+  if (c.top) (void)hipFree(c.top);
   c = DevCanvas();
 }
 
@@ -189,7 +190,10 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
   CVX_HIP(hipSetDevice(ctx->device));
 
   const uint64_t lb = leaf_bytes(desc->leaf_format);
-  const uint64_t rec_bytes = n_nodes * 16, pay_bytes = n_nodes * lb;
+  const uint32_t top_depth = cvx::top_table_depth(desc->R, plan.depth);
+  const uint64_t top_side = (uint64_t)desc->R << top_depth;
+  const uint64_t top_bytes = top_depth ? top_side * top_side * top_side * 4 : 0;
+  const uint64_t rec_bytes = n_nodes * 16, pay_bytes = n_nodes * lb + top_bytes;
   const uint64_t tmp_bytes = n_nodes * 8 + std::max<uint64_t>(n_leaves, 1) * lb +
                              std::max<uint64_t>(plan.order.size(), 1) * 4;
   size_t free_b = 0, total_b = 0;
@@ -217,7 +221,8 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
     if (e != hipSuccess) where = #call; \
   }
   STEP(hipMalloc(&nc.rec, rec_bytes));
-  STEP(hipMalloc(&nc.pay, pay_bytes));
+  STEP(hipMalloc(&nc.pay, n_nodes * lb));
+  if (top_bytes) STEP(hipMalloc((void**)&nc.top, top_bytes));
   STEP(hipMalloc(&raw, n_nodes * 8));
   STEP(hipMalloc(&rawl, std::max<uint64_t>(n_leaves, 1) * lb));
   STEP(hipMalloc(&ord, std::max<uint64_t>(plan.order.size(), 1) * 4));
@@ -226,7 +231,7 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
     return fail(ctx, CVX_ERR_OOM, "device allocation failed");
   }
   STEP(hipMemsetAsync(nc.rec, 0, rec_bytes, ctx->stream));
-  STEP(hipMemsetAsync(nc.pay, 0, pay_bytes, ctx->stream));
+  STEP(hipMemsetAsync(nc.pay, 0, n_nodes * lb, ctx->stream));
   STEP(hipMemcpyAsync(raw, nodes, n_nodes * 8, hipMemcpyHostToDevice, ctx->stream));
   if (n_leaves) STEP(hipMemcpyAsync(rawl, leaves, n_leaves * lb, hipMemcpyHostToDevice, ctx->stream));
   STEP(hipMemcpyAsync(ord, plan.order.data(), plan.order.size() * 4, hipMemcpyHostToDevice,
@@ -238,6 +243,14 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
     if (le != hipSuccess) {
       e = (hipError_t)le;
       where = "k_relayout_level";
+    }
+  }
+  if (e == hipSuccess && top_bytes) {
+    nc.top_depth = top_depth;
+    int le = cvx::launch_top_table(ctx->stream, nc.rec, n_nodes, desc->R, top_depth, nc.top);
+    if (le != hipSuccess) {
+      e = (hipError_t)le;
+      where = "k_top_table";
     }
   }
   STEP(hipStreamSynchronize(ctx->stream));
@@ -292,6 +305,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     return fail(ctx, CVX_ERR_INVALID_ARG, "wg_size must be 64, 128 or 256");
   uint32_t wgs = o.workgroups ? o.workgroups : (uint32_t)ctx->n_cu * (2048u / wg);
   if (wgs > (1u << 20)) return fail(ctx, CVX_ERR_INVALID_ARG, "too many workgroups");
+  if (o.top_lookup > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "top_lookup must be 0 or 1");
   if (o.out_f64 && o.variant != CVX_VARIANT_FP64_PLAIN)
     return fail(ctx, CVX_ERR_INVALID_ARG, "out_f64 needs the FP64_PLAIN variant");
   const cvx_trace* tr = o.trace;
@@ -370,6 +384,9 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     uint64_t cap = 3ull * c.desc.R * (1ull << std::min<uint32_t>(c.depth, 40)) + 16;
     dv.max_steps = (uint32_t)std::min<uint64_t>(cap, 1ull << 22);
     dv.n_nodes = (uint32_t)c.n_nodes;
+    const bool top = o.top_lookup == 0 && c.top_depth > 0;
+    dv.top_depth = top ? c.top_depth : 0;
+    dv.top = top ? c.top : nullptr;
   }
   CastHeader& H = *ctx->h_hdr;
   H.total_work = tr ? (tr->n + 63) / 64 : first;
@@ -458,6 +475,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
   static const uint32_t kTiles[][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}};
   static const uint32_t kWg[] = {64, 128, 256};
   static const uint32_t kWavesPerCu[] = {16, 28, 32, 64};
+  static const uint32_t kTop[] = {0, 1};
   CVX_HIP(hipSetDevice(ctx->device));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CVX_HIP(hipEventCreate(&e0));
@@ -470,6 +488,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
   float best_ms = 0.0f;
   bool have = false;
   uint32_t count = 0;
+  for (uint32_t top : kTop) {
   for (const auto& t : kTiles) {
     for (uint32_t wg : kWg) {
       for (uint32_t wpc : kWavesPerCu) {
@@ -479,6 +498,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         o.tile_h = t[1];
         o.wg_size = wg;
         o.workgroups = (uint32_t)ctx->n_cu * wpc * 64u / wg;
+        o.top_lookup = top;
         rc = cvx_render(ctx, views, n_views, out_dev, &o);  // warm-up, captures the graph
         if (rc != CVX_OK) break;
         if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess) {
@@ -503,7 +523,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
           x.wg_size = o.wg_size;
           x.workgroups = o.workgroups;
           x.ms = ms;
-          x.reserved = 0;
+          x.top_lookup = o.top_lookup;
         }
         ++count;
         if (!have || ms < best_ms) {
@@ -513,6 +533,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         }
       }
     }
+  }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -54,12 +54,14 @@ __device__ __forceinline__ void set(V3<T>& v, int k, T a) {
 
 struct Acc {
   uint32_t rays, leaves, outer, descent, fp64_exit, rebase;
+  uint64_t steps, slots;  // loop iterations of the lanes; 64 x the longest lane per tile
 };
 
 struct Out {
   double rgba[4];
   uint32_t flags;
   uint32_t n;
+  uint32_t steps;  // loop iterations of this ray
 };
 
 // Trace sink: records (leaf, l) pairs when tracing is on.
@@ -168,6 +170,78 @@ __device__ __forceinline__ bool descend(const void* rec, uint32_t n_nodes, const
     r = ld_rec(rec, I);
   }
   return true;
+}
+
+// Integer point location.  The FP64 point q (canvas units, inside [0, R]^3)
+// maps to the coordinates of its cell at the deepest level D:
+//   C_k = floor(q_k 2^D), one less when q_k 2^D is an integer and the ray
+//   moves down axis k,
+// clamped to the canvas.  q_k 2^D and its floor are exact in FP64 (R 2^D <=
+// 2^30).  For a cell containing q, the child on axis k is the upper one iff
+// q_k > mid or (q_k = mid and the ray moves up axis k) (ties go to the side
+// the ray moves into); with C clamped to the cell this is the matching bit
+// of C, at every level.  So a descent is one clamp and then integer work.
+__device__ __forceinline__ V3<uint32_t> deep_coords(const V3<double>& q, const V3<bool>& up,
+                                                    uint32_t R, uint32_t D) {
+  V3<uint32_t> C;
+  const int32_t hi = (int32_t)((R << D) - 1u);
+  for (int k = 0; k < 3; ++k) {
+    const double Q = ldexp(get(q, k), (int)D);
+    const double f = floor(Q);
+    int32_t n = (int32_t)f;
+    n -= (Q == f && !get(up, k)) ? 1 : 0;
+    n = n < 0 ? 0 : (n > hi ? hi : n);
+    set(C, k, (uint32_t)n);
+  }
+  return C;
+}
+
+// Descend from the current cell (I, dep, c; record r) to the leaf holding the
+// deep coordinates C.  Returns false (and stops) if a child index falls
+// outside the pool.
+__device__ __forceinline__ bool descend_int(const void* rec, uint32_t n_nodes, V3<uint32_t> C,
+                                            uint32_t D, uint32_t& I, uint32_t& dep,
+                                            V3<uint32_t>& c, uint4& r) {
+  if (r.x & 1u) return true;
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t lo = get(c, k) << (D - dep);
+    const uint32_t hi = lo + ((1u << (D - dep)) - 1u);
+    const uint32_t ck = get(C, k);
+    set(C, k, ck < lo ? lo : (ck > hi ? hi : ck));
+  }
+  while (!(r.x & 1u)) {
+    if (r.x >= n_nodes - 7u) return false;
+    const uint32_t sh = D - dep - 1u;
+    uint32_t oct = 0;
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t b = (get(C, k) >> sh) & 1u;
+      oct |= b << k;
+      set(c, k, 2u * get(c, k) + b);
+    }
+    I = r.x + oct;
+    ++dep;
+    r = ld_rec(rec, I);
+  }
+  return true;
+}
+
+// Cell of a ray start: through the top-level table when the view has one
+// (the node of depth <= L covering the depth-L cell of C), else the root.
+__device__ __forceinline__ void locate_top(const DView& v, const V3<uint32_t>& C, uint32_t& I,
+                                           uint32_t& dep, V3<uint32_t>& c, uint4& r) {
+  const uint32_t D = v.max_depth;
+  if (v.top_depth) {
+    const uint32_t L = v.top_depth, side = v.R << L;
+    const uint32_t x = C.x >> (D - L), y = C.y >> (D - L), z = C.z >> (D - L);
+    I = v.top[x + side * (y + side * z)];
+    r = ld_rec(v.rec, I);
+    dep = (r.x & 1u) ? ((r.x >> 1) & 63u) : L;
+  } else {
+    I = (C.x >> D) + v.R * ((C.y >> D) + v.R * (C.z >> D));
+    r = ld_rec(v.rec, I);
+    dep = 0;
+  }
+  c = V3<uint32_t>{C.x >> (D - dep), C.y >> (D - dep), C.z >> (D - dep)};
 }
 
 // Root cell containing q (ties go to the side the ray moves into).
@@ -303,8 +377,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   }
   uint32_t I, dep = 0;
   V3<uint32_t> c;
-  root_of<double>(q, up, v.R, c, I);
-  uint4 r = ld_rec(rec, I);
+  uint4 r;
+  locate_top(v, deep_coords(q, up, v.R, v.max_depth), I, dep, c, r);
+  if (STATS) acc.descent += dep;
   uint2 pay = make_uint2(0u, 0u);
 
   uint32_t db = 0, w = 1;
@@ -316,7 +391,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   bool bad = false;  // a node index outside the pool (never for a validated pool)
   auto rebase = [&](double te) __attribute__((always_inline)) {
     const uint32_t d0 = dep;
-    bad = bad || !descend<double>(rec, v.n_nodes, q, up, I, dep, c, r);
+    bad = bad || !descend_int(rec, v.n_nodes, deep_coords(q, up, v.R, v.max_depth), v.max_depth,
+                              I, dep, c, r);
     if (STATS) acc.descent += dep - d0;
     pay = ld_pay(payp, I);
     db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
@@ -342,7 +418,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   uint32_t n_rec = 0;
   int ke = en.kin;  // axis of the face the current cell was entered through
   uint32_t rstride[3] = {1u, v.R, v.R * v.R};
-  for (uint32_t step = 0;; ++step) {
+  uint32_t step = 0;
+  for (;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
     if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
     // s-values of the far planes (leaf) or of the mid-planes (refined cell)
@@ -499,6 +576,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   out.rgba[2] = C.z * k255;
   out.rgba[3] = 1.0f - T;
   out.n = n_rec;
+  out.steps = step + 1;
   if (STATS) acc.leaves += n_rec;
 }
 
@@ -523,15 +601,17 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
   }
   uint32_t I, dep = 0;
   V3<uint32_t> c;
-  root_of<double>(q, up, v.R, c, I);
-  uint4 r = ld_rec(rec, I);
-  bool bad = !descend<double>(rec, v.n_nodes, q, up, I, dep, c, r);
+  uint4 r;
+  const V3<uint32_t> C0 = deep_coords(q, up, v.R, v.max_depth);
+  locate_top(v, C0, I, dep, c, r);
+  bool bad = !descend_int(rec, v.n_nodes, C0, v.max_depth, I, dep, c, r);
   if (STATS) acc.descent += dep;
   double T = 1.0;
   V3<double> C{0.0, 0.0, 0.0};
   double t_ent = en.t0;
   uint32_t n_rec = 0;
-  for (uint32_t step = 0;; ++step) {
+  uint32_t step = 0;
+  for (;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
     if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
     const double h = ldexp(1.0, -(int)dep);
@@ -594,6 +674,7 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
   out.rgba[2] = C.z;
   out.rgba[3] = 1.0 - T;
   out.n = n_rec;
+  out.steps = step + 1;
   if (STATS) acc.leaves += n_rec;
 }
 
@@ -625,7 +706,8 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
   float T = 1.0f;
   V3<float> C{0.f, 0.f, 0.f};
   uint32_t n_rec = 0;
-  for (uint32_t step = 0;; ++step) {
+  uint32_t step = 0;
+  for (;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
     if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
     const float h = ldexpf(1.0f, -(int)dep);
@@ -679,6 +761,7 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
   out.rgba[2] = C.z * k255;
   out.rgba[3] = 1.0f - T;
   out.n = n_rec;
+  out.steps = step + 1;
   if (STATS) acc.leaves += n_rec;
 }
 
@@ -690,6 +773,7 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
   out.flags = 0;
   out.n = 0;
+  out.steps = 0;
   if (STATS) acc.rays++;
   const Entry en = canvas_entry(o, d, (double)v.R);
   if (!en.hit) return;
@@ -721,7 +805,7 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t total = a.hdr->total_work;
   const uint32_t nv = a.hdr->n_views;
-  Acc acc = {0, 0, 0, 0, 0, 0};
+  Acc acc = {0, 0, 0, 0, 0, 0, 0, 0};
   for (;;) {
     uint32_t w = 0;
     if (lane == 0) w = atomicAdd(&a.hdr->queue, 1u);
@@ -730,6 +814,7 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
     w = __builtin_amdgcn_readfirstlane(w);
     if ((uint64_t)w >= total) break;
     Out res;
+    res.steps = 0;
     if constexpr (!TRACE) {
       int lo = 0, hi = (int)nv - 1;
       while (lo < hi) {
@@ -775,11 +860,23 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
         }
       }
     }
+    if constexpr (STATS) {
+      // every lane of the wavefront is here: the tile took as many
+      // iterations as its longest ray
+      uint32_t m = res.steps;
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+      }
+      acc.steps += res.steps;
+      acc.slots += m;
+    }
   }
   if constexpr (STATS) {
-    const uint32_t vals[6] = {acc.rays, acc.leaves, acc.outer, acc.descent, acc.fp64_exit, acc.rebase};
-    for (int s = 0; s < 6; ++s) {
-      uint32_t x = vals[s];
+    const uint64_t vals[8] = {acc.rays, acc.leaves, acc.outer, acc.descent,
+                              acc.fp64_exit, acc.rebase, acc.steps, acc.slots};
+    for (int s = 0; s < 8; ++s) {
+      unsigned long long x = vals[s];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
       if (lane == 0 && x) atomicAdd((unsigned long long*)&a.stats[s], (unsigned long long)x);
     }

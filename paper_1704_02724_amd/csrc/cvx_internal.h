@@ -38,8 +38,18 @@ struct DevCanvas {
   uint32_t depth = 0;     // deepest level present
   void* rec = nullptr;    // uint4 per node
   void* pay = nullptr;    // uint2 or double4 per node
+  uint32_t* top = nullptr;  // top-level table: node covering each cell of depth top_depth
+  uint32_t top_depth = 0;   // 0: no table
   uint64_t bytes = 0;
 };
+
+// Depth of the top-level table of a canvas: at most 6 levels and 2^18 cells,
+// never below the deepest level present; 0 means no table.
+inline uint32_t top_table_depth(uint32_t R, uint32_t depth) {
+  uint32_t L = depth < 6 ? depth : 6;
+  while (L > 0 && ((uint64_t)R << L) * ((uint64_t)R << L) * ((uint64_t)R << L) > (1ull << 18)) --L;
+  return L;
+}
 
 // Per-view parameters in device memory (host computes them once per render).
 struct DView {
@@ -55,7 +65,8 @@ struct DView {
   float alpha_stop;
   uint32_t max_steps;
   uint32_t n_nodes;     // node ids at or above this are never loaded
-  uint32_t pad;
+  uint32_t top_depth;   // 0: ray starts descend from the root array
+  const uint32_t* top;  // (R 2^top_depth)^3 node ids, x fastest
 };
 
 // Launch-invariant header in device memory, so a captured graph can be
@@ -86,6 +97,8 @@ struct CastArgs {
 };
 
 // kernel launchers (cvx_upload.hip, cvx_cast.hip); return a hipError_t value
+int launch_top_table(void* stream, const void* rec, uint64_t n_nodes, uint32_t R, uint32_t L,
+                     uint32_t* top);
 int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, uint64_t end,
                           uint32_t level, const void* raw_nodes, const void* raw_leaves,
                           uint32_t fmt, void* rec, void* pay, uint32_t R);

@@ -75,6 +75,37 @@ __global__ void k_relayout_level(const uint32_t* __restrict__ order, uint64_t be
   rec[I] = r;
 }
 
+// Top-level table (Sec. 4: the canvas is a uniform array of roots): for every
+// cell of depth L, x fastest, the node of depth <= L that covers it (a leaf
+// above L, or the depth-L node itself).  One thread per cell walks down from
+// its root by the bits of its coordinates.
+__global__ void k_top_table(const uint4* __restrict__ rec, uint64_t n_nodes, uint32_t R,
+                            uint32_t L, uint32_t* __restrict__ top) {
+  const uint32_t side = R << L;
+  const uint64_t n = (uint64_t)side * side * side;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t x = (uint32_t)(i % side), y = (uint32_t)((i / side) % side),
+                 z = (uint32_t)(i / ((uint64_t)side * side));
+  uint32_t I = (x >> L) + R * ((y >> L) + R * (z >> L));
+  for (uint32_t lvl = 0; lvl < L; ++lvl) {
+    const uint32_t cx = rec[I].x;
+    if ((cx & 1u) || (uint64_t)cx + 8 > n_nodes) break;
+    const uint32_t sh = L - 1 - lvl;
+    I = cx + (((x >> sh) & 1u) | (((y >> sh) & 1u) << 1) | (((z >> sh) & 1u) << 2));
+  }
+  top[i] = I;
+}
+
+int launch_top_table(void* stream, const void* rec, uint64_t n_nodes, uint32_t R, uint32_t L,
+                     uint32_t* top) {
+  const uint64_t side = (uint64_t)R << L, n = side * side * side;
+  const uint32_t bs = 256;
+  hipLaunchKernelGGL(k_top_table, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, (const uint4*)rec, n_nodes, R, L, top);
+  return (int)hipGetLastError();
+}
+
 int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, uint64_t end,
                           uint32_t level, const void* raw_nodes, const void* raw_leaves,
                           uint32_t fmt, void* rec, void* pay, uint32_t R) {

@@ -38,7 +38,7 @@ CVX_RAYFLAG_STEP_CAP = 1
 CVX_RAYFLAG_FP64_EXIT = 2
 CVX_RAYFLAG_BAD_LINK = 4
 
-CVX_STAT_NAMES = ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase"]
+CVX_STAT_NAMES = ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase", "steps", "slots"]
 CVX_STAT_COUNT = 8
 
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",
@@ -72,14 +72,14 @@ class cvx_render_opts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_uint32), ("tile_w", ctypes.c_uint32),
                 ("tile_h", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
                 ("wg_size", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
-                ("out_f64", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("out_f64", ctypes.c_uint32), ("top_lookup", ctypes.c_uint32),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
 class cvx_tune_result(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_uint32), ("tile_h", ctypes.c_uint32),
                 ("wg_size", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+                ("ms", ctypes.c_float), ("top_lookup", ctypes.c_uint32)]
 
 
 class CvxError(RuntimeError):
@@ -178,8 +178,9 @@ def cvx_render(ctx, views, out_ptr, opts=None):
                                 ctypes.byref(o)))
 
 
-def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=64):
-    """Returns (best cvx_render_opts, list of (tile_w, tile_h, wg_size, workgroups, ms))."""
+def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=128):
+    """Returns (best cvx_render_opts, list of (tile_w, tile_h, wg_size, workgroups, ms,
+    top_lookup))."""
     b = base if base is not None else cvx_render_opts()
     best = cvx_render_opts()
     res = (cvx_tune_result * max_results)()
@@ -187,7 +188,7 @@ def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=64):
     _check(ctx, _lib.cvx_autotune(ctx, ctypes.cast(views, _vp), len(views), _vp(int(out_ptr)),
                                   ctypes.byref(b), int(reps), ctypes.byref(best), res,
                                   int(max_results), ctypes.byref(n)))
-    rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms))
+    rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms), r.top_lookup)
             for r in res[:min(n.value, max_results)]]
     return best, rows
 
@@ -231,8 +232,9 @@ def cvx_validate_views(views, descs):
 
 
 def make_opts(variant="fp32_rebased", tile=(0, 0), workgroups=0, wg_size=0, use_graph=False,
-              out_f64=False, trace=None, stats_ptr=0):
+              out_f64=False, trace=None, stats_ptr=0, top_lookup=0):
     o = cvx_render_opts()
+    o.top_lookup = int(top_lookup)
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.workgroups, o.wg_size = int(workgroups), int(wg_size)

@@ -143,9 +143,25 @@ def test_determinism_across_tuning(sess):
     w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=101, H=77)
     sess.upload(0, w.canvases[0])
     ref = sess.render(w.views, "fp32_rebased").cpu().numpy()
-    for tile, wgs, wg in [((16, 4), 1, 64), ((64, 1), 7, 128), ((4, 16), 0, 256), ((32, 2), 3, 256)]:
-        img = sess.render(w.views, "fp32_rebased", tile=tile, workgroups=wgs, wg_size=wg)
+    for tile, wgs, wg, top in [((16, 4), 1, 64, 0), ((64, 1), 7, 128, 1), ((4, 16), 0, 256, 1),
+                               ((32, 2), 3, 256, 0)]:
+        img = sess.render(w.views, "fp32_rebased", tile=tile, workgroups=wgs, wg_size=wg,
+                          top_lookup=top)
         np.testing.assert_array_equal(img.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("R,depth,seed", [(1, 9, 61), (2, 7, 62), (3, 6, 63)])
+def test_top_table_matches_root_descent(sess, R, depth, seed):
+    """Ray starts located through the top-level table or from the root array
+    give the same images and the same leaf sequences."""
+    cv = trees.random_tree(R, depth, seed=seed, max_nodes=40000, leaf_format=LEAF_RGBA8_F16)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    views = _views_around(rng, 3, 40, 24, inside=True)
+    sess.upload(0, cv)
+    for var in ("fp32_rebased", "fp64_plain"):
+        a = sess.render(views, var, top_lookup=0).cpu().numpy()
+        b = sess.render(views, var, top_lookup=1).cpu().numpy()
+        np.testing.assert_array_equal(a, b)
 
 
 def test_graph_replay_matches_eager(sess):
@@ -215,6 +231,8 @@ def test_stats_match_oracle_counts(sess):
         assert s[1] == orc["n_leaves"].sum()
         links = (orc["alg_bytes"] - 16 - 8 * orc["n_leaves"].astype(np.float64)) / 4
         assert s[2] + s[3] == links.sum()
+        # loop iterations cover every leaf; lane slots are whole 64-lane tiles
+        assert s[6] >= s[1] and s[7] >= s[6] and s[7] % 64 == 0
 
 
 def test_error_paths(sess):
@@ -254,11 +272,13 @@ def test_autotune_picks_a_timed_shape_and_keeps_the_image(sess):
     tuning, rows = sess.autotune(w.views, "fp32_rebased", out=out, reps=2)
     sess.torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), ref)
-    assert len(rows) == 4 * 3 * 4
+    assert len(rows) == 2 * 4 * 3 * 4
     assert {(r[0], r[1]) for r in rows} == {(8, 8), (16, 4), (4, 16), (32, 2)}
+    assert {r[5] for r in rows} == {0, 1}
     assert all(r[4] > 0.0 for r in rows)
     best = min(rows, key=lambda r: r[4])
-    assert tuning == dict(tile=(best[0], best[1]), workgroups=best[3], wg_size=best[2])
+    assert tuning == dict(tile=(best[0], best[1]), workgroups=best[3], wg_size=best[2],
+                          top_lookup=best[5])
     img = sess.render(w.views, "fp32_rebased", use_graph=True, **tuning)
     np.testing.assert_array_equal(img.cpu().numpy(), ref)
     varr = cvx.make_views(w.views)
