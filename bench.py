@@ -202,8 +202,14 @@ def main():
         t = time.perf_counter()
         tuning, tune_rows = sess.autotune(views, args.variant, reps=args.tune_reps)
         log(f"autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; fastest: "
-            + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}: {r[4]:.3f}ms"
+            + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}/q{r[6]}: {r[4]:.3f}ms"
                         for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
+        by = {}
+        for r in tune_rows:
+            key = f"top{r[5]}/q{r[6]}"
+            by[key] = min(by.get(key, 1e30), r[4])
+        log("autotune best per (top lookup, queue) choice: "
+            + ", ".join(f"{k}: {v:.3f}ms" for k, v in sorted(by.items())))
         if args.fp64_steps > 0:
             tuning64, _ = sess.autotune(views, "fp64_plain", reps=max(1, args.tune_reps - 2))
             log(f"autotune fp64_plain: {tuning64}")
@@ -303,6 +309,7 @@ def main():
             "workgroups": int(tuning["workgroups"]),
             "wg_size": int(tuning["wg_size"]),
             "top_lookup": int(tuning.get("top_lookup", 0)),
+            "single_queue": int(tuning.get("single_queue", 0)),
             "autotuned": not args.no_autotune,
             "graph": True,
         },

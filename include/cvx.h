@@ -140,6 +140,10 @@ typedef struct {
   uint32_t out_f64;     /* FP64_PLAIN only: out is double RGBA instead of float */
   uint32_t top_lookup;  /* 0: ray starts are located through the pool's top-level table;
                            1: they descend from the root array (same result) */
+  uint32_t single_queue; /* 0: the tiles are split into 8 contiguous ranges, one per XCD
+                            (workgroup i starts on range i mod 8, then helps the others);
+                            1: one queue over all tiles (same result) */
+  uint32_t reserved2;
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;
@@ -189,13 +193,15 @@ typedef struct {
   uint32_t workgroups;     /* persistent grid size */
   float ms;                /* mean time of one render, milliseconds */
   uint32_t top_lookup;     /* as in cvx_render_opts */
+  uint32_t single_queue;   /* as in cvx_render_opts */
+  uint32_t reserved;
 } cvx_tune_result;
 
 /* Autotuner of the batch scheduler's launch shape: renders `views` exactly as
  * cvx_render would with base's variant and use_graph, once per candidate
  * tile shape (8x8, 16x4, 4x16, 32x2), workgroup size (64, 128, 256),
- * persistent grid (16, 28, 32, 64 wavefronts per CU) and top-level lookup
- * (on, off), one untimed warm-up
+ * persistent grid (16, 28, 32, 64 wavefronts per CU), top-level lookup
+ * (on, off) and work queues (per XCD, single), one untimed warm-up
  * then `reps` renders timed with HIP events on the context stream.  Writes
  * base with the fastest shape filled in to *best and, when results is not
  * NULL, up to max_results timed candidates in the order tried (the count

@@ -306,6 +306,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   uint32_t wgs = o.workgroups ? o.workgroups : (uint32_t)ctx->n_cu * (2048u / wg);
   if (wgs > (1u << 20)) return fail(ctx, CVX_ERR_INVALID_ARG, "too many workgroups");
   if (o.top_lookup > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "top_lookup must be 0 or 1");
+  if (o.single_queue > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "single_queue must be 0 or 1");
   if (o.out_f64 && o.variant != CVX_VARIANT_FP64_PLAIN)
     return fail(ctx, CVX_ERR_INVALID_ARG, "out_f64 needs the FP64_PLAIN variant");
   const cvx_trace* tr = o.trace;
@@ -392,7 +393,8 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   H.total_work = tr ? (tr->n + 63) / 64 : first;
   H.n_rays = tr ? tr->n : 0;
   H.n_views = (uint32_t)n_views;
-  H.queue = 0;
+  H.n_queues = o.single_queue ? 1u : cvx::CVX_NQ;
+  for (auto& q : H.queue) q.next = 0;
   if (H.total_work >= (1ull << 32)) return fail(ctx, CVX_ERR_INVALID_ARG, "too much work in one call");
   CVX_HIP(hipMemcpyAsync(ctx->d_views, ctx->h_views, sizeof(DView) * n_views,
                          hipMemcpyHostToDevice, ctx->stream));
@@ -476,6 +478,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
   static const uint32_t kWg[] = {64, 128, 256};
   static const uint32_t kWavesPerCu[] = {16, 28, 32, 64};
   static const uint32_t kTop[] = {0, 1};
+  static const uint32_t kQueue[] = {0, 1};
   CVX_HIP(hipSetDevice(ctx->device));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CVX_HIP(hipEventCreate(&e0));
@@ -488,6 +491,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
   float best_ms = 0.0f;
   bool have = false;
   uint32_t count = 0;
+  for (uint32_t sq : kQueue) {
   for (uint32_t top : kTop) {
   for (const auto& t : kTiles) {
     for (uint32_t wg : kWg) {
@@ -499,6 +503,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         o.wg_size = wg;
         o.workgroups = (uint32_t)ctx->n_cu * wpc * 64u / wg;
         o.top_lookup = top;
+        o.single_queue = sq;
         rc = cvx_render(ctx, views, n_views, out_dev, &o);  // warm-up, captures the graph
         if (rc != CVX_OK) break;
         if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess) {
@@ -524,6 +529,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
           x.workgroups = o.workgroups;
           x.ms = ms;
           x.top_lookup = o.top_lookup;
+          x.single_queue = o.single_queue;
         }
         ++count;
         if (!have || ms < best_ms) {
@@ -533,6 +539,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         }
       }
     }
+  }
   }
   }
   (void)hipEventDestroy(e0);

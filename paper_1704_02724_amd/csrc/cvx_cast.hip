@@ -801,18 +801,27 @@ __device__ __forceinline__ DView uniform_view(const DView& v) {
 }
 
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
-__global__ __launch_bounds__(256) void k_cast(CastArgs a) {
+__device__ __forceinline__ void cast_grid(const CastArgs& a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t total = a.hdr->total_work;
   const uint32_t nv = a.hdr->n_views;
   Acc acc = {0, 0, 0, 0, 0, 0, 0, 0};
+  const uint32_t nq = a.hdr->n_queues;  // 1 or CVX_NQ (a power of two)
+  uint32_t qi = blockIdx.x & (nq - 1u), drained = 0;
   for (;;) {
-    uint32_t w = 0;
-    if (lane == 0) w = atomicAdd(&a.hdr->queue, 1u);
+    // next item of range qi; an exhausted range passes on to the next one
+    const uint64_t q_lo = total * qi / nq, q_hi = total * (qi + 1u) / nq;
+    uint32_t taken = 0;
+    if (lane == 0) taken = atomicAdd(&a.hdr->queue[qi].next, 1u);
     // every lane is active here (the loop exit is uniform), so the first
     // active lane is lane 0
-    w = __builtin_amdgcn_readfirstlane(w);
-    if ((uint64_t)w >= total) break;
+    taken = __builtin_amdgcn_readfirstlane(taken);
+    if (q_lo + taken >= q_hi) {
+      if (++drained == nq) break;
+      qi = (qi + 1u) & (nq - 1u);
+      continue;
+    }
+    const uint32_t w = (uint32_t)(q_lo + taken);
     Out res;
     res.steps = 0;
     if constexpr (!TRACE) {
@@ -883,15 +892,33 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
   }
 }
 
+template <int VAR, bool TRACE, bool STATS, bool OUT64>
+__global__ __launch_bounds__(256) void k_cast(CastArgs a) {
+  cast_grid<VAR, TRACE, STATS, OUT64>(a);
+}
+
+// The FP64 caster keeps its direction, reciprocal and eye in registers (they
+// enter every step); in render mode five wavefronts per SIMD fit without
+// spills (trace and stats instances use k_cast).
+template <bool TRACE, bool STATS, bool OUT64>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_cast64(
+    CastArgs a) {
+  cast_grid<(int)CVX_VARIANT_FP64_PLAIN, TRACE, STATS, OUT64>(a);
+}
+
 __global__ void k_reset(CastHeader* hdr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->queue = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < CVX_NQ) hdr->queue[threadIdx.x].next = 0u;
 }
 
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
 int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
   const size_t lds = VAR == (int)CVX_VARIANT_FP32_REBASED ? 6u * sizeof(double) * wg_size : 0u;
-  hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
-                     (hipStream_t)stream, a);
+  if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN && !TRACE && !STATS)
+    hipLaunchKernelGGL((k_cast64<TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
+                       (hipStream_t)stream, a);
+  else
+    hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
+                       (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -69,13 +69,26 @@ struct DView {
   const uint32_t* top;  // (R 2^top_depth)^3 node ids, x fastest
 };
 
+// Work queues: the work items (tiles or 64-ray chunks) are split into
+// CVX_NQ contiguous ranges, one per XCD (a workgroup runs on XCD
+// blockIdx.x mod 8), so the tiles one XCD renders are neighbours and share
+// its L2.  A wavefront drains its own range first, then the others in turn.
+constexpr uint32_t CVX_NQ = 8;
+
+struct alignas(128) QueueHead {
+  uint32_t next;  // items taken from this range so far
+  uint32_t pad[31];
+};
+
 // Launch-invariant header in device memory, so a captured graph can be
 // replayed for any view set of the same launch shape.
 struct CastHeader {
   uint64_t total_work;  // tiles (render) or 64-ray chunks (trace)
   uint64_t n_rays;      // trace mode: number of listed rays
   uint32_t n_views;
-  uint32_t queue;       // work-queue head, reset by a kernel before each cast
+  uint32_t n_queues;        // 1 or CVX_NQ ranges in use
+  uint32_t pad[26];
+  QueueHead queue[CVX_NQ];  // reset by a kernel before each cast
 };
 
 struct CastArgs {

@@ -73,13 +73,15 @@ class cvx_render_opts(ctypes.Structure):
                 ("tile_h", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
                 ("wg_size", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
                 ("out_f64", ctypes.c_uint32), ("top_lookup", ctypes.c_uint32),
+                ("single_queue", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
 class cvx_tune_result(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_uint32), ("tile_h", ctypes.c_uint32),
                 ("wg_size", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
-                ("ms", ctypes.c_float), ("top_lookup", ctypes.c_uint32)]
+                ("ms", ctypes.c_float), ("top_lookup", ctypes.c_uint32),
+                ("single_queue", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class CvxError(RuntimeError):
@@ -178,9 +180,9 @@ def cvx_render(ctx, views, out_ptr, opts=None):
                                 ctypes.byref(o)))
 
 
-def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=128):
+def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
     """Returns (best cvx_render_opts, list of (tile_w, tile_h, wg_size, workgroups, ms,
-    top_lookup))."""
+    top_lookup, single_queue))."""
     b = base if base is not None else cvx_render_opts()
     best = cvx_render_opts()
     res = (cvx_tune_result * max_results)()
@@ -188,8 +190,8 @@ def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=128):
     _check(ctx, _lib.cvx_autotune(ctx, ctypes.cast(views, _vp), len(views), _vp(int(out_ptr)),
                                   ctypes.byref(b), int(reps), ctypes.byref(best), res,
                                   int(max_results), ctypes.byref(n)))
-    rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms), r.top_lookup)
-            for r in res[:min(n.value, max_results)]]
+    rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms), r.top_lookup,
+             r.single_queue) for r in res[:min(n.value, max_results)]]
     return best, rows
 
 
@@ -232,9 +234,10 @@ def cvx_validate_views(views, descs):
 
 
 def make_opts(variant="fp32_rebased", tile=(0, 0), workgroups=0, wg_size=0, use_graph=False,
-              out_f64=False, trace=None, stats_ptr=0, top_lookup=0):
+              out_f64=False, trace=None, stats_ptr=0, top_lookup=0, single_queue=0):
     o = cvx_render_opts()
     o.top_lookup = int(top_lookup)
+    o.single_queue = int(single_queue)
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.workgroups, o.wg_size = int(workgroups), int(wg_size)

@@ -143,10 +143,11 @@ def test_determinism_across_tuning(sess):
     w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=101, H=77)
     sess.upload(0, w.canvases[0])
     ref = sess.render(w.views, "fp32_rebased").cpu().numpy()
-    for tile, wgs, wg, top in [((16, 4), 1, 64, 0), ((64, 1), 7, 128, 1), ((4, 16), 0, 256, 1),
-                               ((32, 2), 3, 256, 0)]:
+    for tile, wgs, wg, top, sq in [((16, 4), 1, 64, 0, 0), ((64, 1), 7, 128, 1, 1),
+                                   ((4, 16), 0, 256, 1, 0), ((32, 2), 3, 256, 0, 1),
+                                   ((8, 8), 13, 64, 0, 0)]:
         img = sess.render(w.views, "fp32_rebased", tile=tile, workgroups=wgs, wg_size=wg,
-                          top_lookup=top)
+                          top_lookup=top, single_queue=sq)
         np.testing.assert_array_equal(img.cpu().numpy(), ref)
 
 
@@ -272,13 +273,13 @@ def test_autotune_picks_a_timed_shape_and_keeps_the_image(sess):
     tuning, rows = sess.autotune(w.views, "fp32_rebased", out=out, reps=2)
     sess.torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), ref)
-    assert len(rows) == 2 * 4 * 3 * 4
+    assert len(rows) == 2 * 2 * 4 * 3 * 4
     assert {(r[0], r[1]) for r in rows} == {(8, 8), (16, 4), (4, 16), (32, 2)}
-    assert {r[5] for r in rows} == {0, 1}
+    assert {r[5] for r in rows} == {0, 1} and {r[6] for r in rows} == {0, 1}
     assert all(r[4] > 0.0 for r in rows)
     best = min(rows, key=lambda r: r[4])
     assert tuning == dict(tile=(best[0], best[1]), workgroups=best[3], wg_size=best[2],
-                          top_lookup=best[5])
+                          top_lookup=best[5], single_queue=best[6])
     img = sess.render(w.views, "fp32_rebased", use_graph=True, **tuning)
     np.testing.assert_array_equal(img.cpu().numpy(), ref)
     varr = cvx.make_views(w.views)
