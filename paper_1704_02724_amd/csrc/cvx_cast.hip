@@ -331,10 +331,11 @@ constexpr float ALPHA_C = 0x1p-21f * 1.0625f + 0x1p-23f;
 constexpr float BETA_C = 1.0625f;
 constexpr uint32_t DB_MARGIN = 8;
 
-// Per-lane LDS slot holding the FP64 eye and direction of the lane's ray,
-// [6][blockDim.x] doubles (component-major, so lanes read consecutive words).
-// The FP32 traversal needs them only on its rare FP64 paths; keeping them here
-// instead of in 12 VGPRs raises the number of resident wavefronts.
+// Per-lane LDS slot holding the FP64 eye, direction and reciprocal direction
+// of the lane's ray, [9][blockDim.x] doubles (component-major, so lanes read
+// consecutive words).  The FP32 traversal needs them only on its rare FP64
+// paths; keeping them here instead of in registers raises the number of
+// resident wavefronts.
 extern __shared__ double s_ray[];
 
 typedef __attribute__((address_space(3))) double lds_f64;
@@ -345,9 +346,10 @@ struct RaySlot {
   __device__ __forceinline__ void put(const V3<double>& o, const V3<double>& d) const {
     p[0] = o.x; p[stride] = o.y; p[2 * stride] = o.z;
     p[3 * stride] = d.x; p[4 * stride] = d.y; p[5 * stride] = d.z;
+    p[6 * stride] = 1.0 / d.x; p[7 * stride] = 1.0 / d.y; p[8 * stride] = 1.0 / d.z;
   }
-  // component j (0-2 eye, 3-5 direction), read through an opaque pointer so
-  // the load stays on the rare path that needs it
+  // component j (0-2 eye, 3-5 direction, 6-8 reciprocal direction), read
+  // through an opaque pointer so the load stays on the rare path that needs it
   __device__ __forceinline__ double at(int j) const { return opaque(p)[j * stride]; }
 };
 
@@ -418,6 +420,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   uint32_t n_rec = 0;
   int ke = en.kin;  // axis of the face the current cell was entered through
   uint32_t rstride[3] = {1u, v.R, v.R * v.R};
+  // travel direction bits (x | y<<1 | z<<2) in one opaque register: the
+  // exit-axis bit is one bit-field extract, not a chain of selects
+  const uint32_t ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
   uint32_t step = 0;
   for (;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
@@ -479,15 +484,15 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       uint32_t nsure = 0;
       for (int k = 0; k < 3; ++k) nsure += (get(S, k) - Smin > get(eb, k) + emin) ? 1u : 0u;
       if (nsure != 2u) {
-        // FP64 decision from the exact face planes
+        // FP64 decision from the exact face planes, t = (X - o_k) / d_k with
+        // the correctly rounded reciprocal (as the FP64 caster does)
         const double hd = ldexp(1.0, -(int)dep);
         double best = __builtin_inf();
         int kb = kx;
 #pragma unroll 1
         for (int k = 0; k < 3; ++k) {
           const double X = (double)get(c, k) * hd + (get(up, k) ? hd : 0.0);
-          const double dk = slot.at(3 + k);
-          const double tt = dk == 0.0 ? __builtin_inf() : (X - slot.at(k)) / dk;
+          const double tt = get(tD, k) == 0.0f ? __builtin_inf() : (X - slot.at(k)) * slot.at(6 + k);
           kb = tt < best ? k : kb;
           best = tt < best ? tt : best;
         }
@@ -515,18 +520,22 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       ++n_rec;
       // ---- neighbour across the exit face: sibling, next root or G_3 link
       const uint32_t ck = get(c, kx);
-      const bool upk = get(up, kx);
-      const int32_t sk_ = upk ? 1 : -1;
-      const uint32_t nc = ck + (uint32_t)sk_;           // wraps to ~0 below 0
+      const uint32_t upk = (ub >> kx) & 1u;
+      const uint32_t nc = ck + 2u * upk - 1u;            // wraps to ~0 below 0
       const bool at_edge = nc >= (v.R << dep);
       const bool root = dep == 0;
       // the sibling lies across the face when the cell is even going up
-      // (odd going down)
-      const bool inner = !root && (((ck & 1u) == 0u) == upk);
-      uint32_t rs = rstride[0];
-      rs = kx == 1 ? rstride[1] : rs;
-      rs = kx == 2 ? rstride[2] : rs;
-      const uint32_t sib = I + (uint32_t)(sk_ * (int32_t)(root ? rs : (1u << kx)));
+      // (odd going down); siblings differ in octant bit kx only
+      const bool inner = !root && ((ck ^ upk) & 1u) != 0u;
+      uint32_t sib = I ^ (1u << kx);
+      if (root) {
+        // root array (rare): kept as a branch, not flattened into selects
+        asm volatile("");
+        uint32_t rs = rstride[0];
+        rs = kx == 1 ? rstride[1] : rs;
+        rs = kx == 2 ? rstride[2] : rs;
+        sib = upk ? I + rs : I - rs;
+      }
       uint32_t link = r.y;
       link = kx == 1 ? r.z : link;
       link = kx == 2 ? r.w : link;
@@ -912,7 +921,7 @@ __global__ void k_reset(CastHeader* hdr) {
 
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
 int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
-  const size_t lds = VAR == (int)CVX_VARIANT_FP32_REBASED ? 6u * sizeof(double) * wg_size : 0u;
+  const size_t lds = VAR == (int)CVX_VARIANT_FP32_REBASED ? 9u * sizeof(double) * wg_size : 0u;
   if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN && !TRACE && !STATS)
     hipLaunchKernelGGL((k_cast64<TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);
