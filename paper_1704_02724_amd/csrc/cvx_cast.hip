@@ -906,11 +906,20 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
   cast_grid<VAR, TRACE, STATS, OUT64>(a);
 }
 
+// Render-mode entry points with an occupancy target (trace and stats
+// instances use k_cast).  The FP32 caster fits eight wavefronts per SIMD
+// without spills (its LDS slot, 72 B per lane, then fills 147 KB of a CU's
+// 160 KB).
+template <bool OUT64>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_cast32(
+    CastArgs a) {
+  cast_grid<(int)CVX_VARIANT_FP32_REBASED, false, false, OUT64>(a);
+}
+
 // The FP64 caster keeps its direction, reciprocal and eye in registers (they
-// enter every step); in render mode five wavefronts per SIMD fit without
-// spills (trace and stats instances use k_cast).
+// enter every step); seven wavefronts per SIMD fit without spills.
 template <bool TRACE, bool STATS, bool OUT64>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_cast64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_cast64(
     CastArgs a) {
   cast_grid<(int)CVX_VARIANT_FP64_PLAIN, TRACE, STATS, OUT64>(a);
 }
@@ -925,6 +934,8 @@ int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
   if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN && !TRACE && !STATS)
     hipLaunchKernelGGL((k_cast64<TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);
+  else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && !TRACE && !STATS)
+    hipLaunchKernelGGL((k_cast32<OUT64>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream, a);
   else
     hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);
