@@ -125,6 +125,56 @@ def time_per_view(sess, views, variant, steps, tuning):
     return (time.perf_counter() - t0) / steps, out
 
 
+def edit_bench(sess, cv, n_paint, n_refine, n_coarsen, seed):
+    """Times cvx_edit_pool on a second copy of the canvas: one batch of paints,
+    refinements and coarsenings on disjoint nodes (the first call also builds the
+    host mirror of the pool), against a full cvx_upload_pool."""
+    from canvasgen.pool import LEAF, LEAF_DTYPE
+    torch = sess.torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    child = cv.nodes[:, 0]
+    is_leaf = (child & LEAF) != 0
+    internal = np.nonzero(~is_leaf)[0]
+    internal = internal[internal >= 0]
+    kids = child[internal][:, None].astype(np.int64) + np.arange(8)[None, :]
+    ok = np.all(is_leaf[kids], axis=1)
+    coarse = rng.permutation(internal[ok])[:n_coarsen]
+    busy = np.zeros(len(child), bool)
+    busy[(child[coarse][:, None].astype(np.int64) + np.arange(8)[None, :]).ravel()] = True
+    # leaves in the tree: the padding slots after the roots have no parent
+    in_tree = (cv.nodes[:, 1] != 0xFFFFFFFF) | (np.arange(len(child)) < cv.R ** 3)
+    cand = np.nonzero(is_leaf & ~busy & in_tree)[0]
+    pick = rng.permutation(cand)[:n_paint + n_refine]
+    paint, refine = pick[:n_paint], pick[n_paint:]
+    pays = np.zeros(n_paint + 8 * n_refine + n_coarsen, LEAF_DTYPE[cv.leaf_format])
+    if cv.leaf_format == 0:
+        pays["r"], pays["g"], pays["b"] = (rng.integers(0, 256, (3, len(pays)))).astype(np.uint8)
+        pays["kappa"] = np.float16(0.5).view(np.uint16)
+    else:
+        pays["kappa"] = 0.5
+    edits = ([(0, int(n), i) for i, n in enumerate(paint)]
+             + [(1, int(n), n_paint + 8 * i) for i, n in enumerate(refine)]
+             + [(2, int(n), n_paint + 8 * n_refine + i) for i, n in enumerate(coarse)])
+    torch.cuda.synchronize()
+    log(f"pool edits: {len(edits)} edits drawn")
+    t = time.perf_counter()
+    sess.upload(9, cv)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t) * 1e3
+    log(f"pool edits: upload of the copy {upload_ms:.1f} ms")
+    t = time.perf_counter()
+    sess.edit(9, [(0, int(paint[0]), 0)], pays[:1])       # builds the host mirror
+    first_ms = (time.perf_counter() - t) * 1e3
+    log(f"pool edits: first edit (mirror build) {first_ms:.1f} ms")
+    t = time.perf_counter()
+    sess.edit(9, edits, pays)
+    edit_ms = (time.perf_counter() - t) * 1e3
+    sess.free(9)
+    return dict(paint=int(len(paint)), refine=int(len(refine)), coarsen=int(len(coarse)),
+                edit_ms=round(edit_ms, 2), first_edit_ms=round(first_ms, 2),
+                upload_ms=round(upload_ms, 2), nodes=int(cv.n_nodes))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +193,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--workgroups/--wg-size instead of cvx_autotune's pick")
     ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--edit-bench", type=int, default=1,
+                    help="also time one batch of pool edits on the first canvas (0 skips it)")
     ap.add_argument("--per-view-steps", type=int, default=-1,
                     help="steps of the one-launch-per-view comparison (default 3 when the "
                          "workload has more than two views; 0 skips it)")
@@ -273,6 +325,12 @@ def main():
     mean_b_oracle = float(orc["alg_bytes"].mean())
     log(f"parity: {parity}")
 
+    # --- pool edits on a copy of the first canvas
+    edit = None
+    if args.edit_bench:
+        edit = edit_bench(sess, cv[0], 20000, 2000, 500, 99)
+        log(f"pool edits: {edit}")
+
     # --- CPU oracle baseline on a bounded sample
     cpu = None
     if not args.no_cpu:
@@ -332,6 +390,7 @@ def main():
         "fp64_plain_mrays": round(fp64, 2) if fp64 else None,
         "speedup_vs_fp64_plain": round(value / fp64, 3) if fp64 else None,
         "per_view_launches": per_view,
+        "pool_edit": edit,
         "parity": parity,
         "kernel_stats": dict({k: int(v) for k, v in zip(
             ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase", "steps", "slots"], s[:8])},

@@ -213,6 +213,42 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
                  const cvx_render_opts* base, uint32_t reps, cvx_render_opts* best,
                  cvx_tune_result* results, uint32_t max_results, uint32_t* n_results);
 
+/* Pool edits (Sec. 5.1-5.3: a stroke paints leaves, refines leaves down to
+ * the brush resolution and coarsens groups that became uniform; Sec. 4.1.2:
+ * the GPU pools and the neighbour graph G_3 are brought up to date after
+ * every change). */
+#define CVX_EDIT_PAINT 0u   /* node: a leaf; its payload becomes payloads[first_payload] */
+#define CVX_EDIT_REFINE 1u  /* node: a leaf of depth < desc.max_depth; it gets 8 leaf children
+                               (octant order x | y<<1 | z<<2) with payloads
+                               [first_payload, first_payload + 8) */
+#define CVX_EDIT_COARSEN 2u /* node: refined, its 8 children all leaves; it becomes a leaf with
+                               payload payloads[first_payload]; the children's group is freed */
+
+typedef struct {
+  uint32_t op;            /* CVX_EDIT_* */
+  uint32_t node;          /* node id in the current pool */
+  uint64_t first_payload; /* index into the payloads array */
+} cvx_edit;
+
+/* Apply n_edits edits to the pool under canvas_id, in order (an edit sees
+ * the pool the earlier ones produced).  payloads is a host array of
+ * n_payloads leaf records in the pool's leaf format, read during the call.
+ * A refined leaf's children take the most recently freed group of 8 node
+ * ids, else 8 new ids at the end of the pool (which grows; node ids of
+ * existing nodes never change).  If first_child_out is not NULL, it receives
+ * per edit the first child id of a REFINE and CVX_NONE_ID otherwise.  Every
+ * edit is checked first (node state, depth limit, payload index and kappa);
+ * on any error nothing changes.  The records, payloads, the three
+ * outer-face links of every node (rebuilt on the GPU level by level, as at
+ * upload) and the top-level table are updated before the call returns.
+ * Synchronous. */
+#define CVX_NONE_ID 0xffffffffu
+int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n_edits,
+                  const void* payloads, uint64_t n_payloads, uint32_t* first_child_out);
+
+/* Number of node ids of the pool under canvas_id (including freed groups). */
+int cvx_pool_nodes(cvx_ctx* ctx, int canvas_id, uint64_t* n_nodes);
+
 /* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
 int cvx_free_pool(cvx_ctx* ctx, int canvas_id);
 

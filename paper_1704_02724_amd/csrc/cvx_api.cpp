@@ -230,7 +230,8 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
     cleanup();
     return fail(ctx, CVX_ERR_OOM, "device allocation failed");
   }
-  STEP(hipMemsetAsync(nc.rec, 0, rec_bytes, ctx->stream));
+  // nodes outside the tree keep x = CVX_FREE and null links
+  STEP(hipMemsetAsync(nc.rec, 0xff, rec_bytes, ctx->stream));
   STEP(hipMemsetAsync(nc.pay, 0, n_nodes * lb, ctx->stream));
   STEP(hipMemcpyAsync(raw, nodes, n_nodes * 8, hipMemcpyHostToDevice, ctx->stream));
   if (n_leaves) STEP(hipMemcpyAsync(rawl, leaves, n_leaves * lb, hipMemcpyHostToDevice, ctx->stream));
@@ -265,6 +266,7 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
   raw = rawl = ord = nullptr;
   nc.present = true;
   nc.bytes = rec_bytes + pay_bytes;
+  nc.cap_nodes = n_nodes;
   free_canvas(ctx->canvases[canvas_id]);
   ctx->canvases[canvas_id] = nc;
   return CVX_OK;
@@ -458,6 +460,321 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     ctx->gkey = key;
   }
   CVX_HIP(hipGraphLaunch(ctx->gexec, ctx->stream));
+  return CVX_OK;
+}
+
+int cvx_pool_nodes(cvx_ctx* ctx, int canvas_id, uint64_t* n_nodes) {
+  if (!ctx || !n_nodes) return CVX_ERR_INVALID_ARG;
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  if (!ctx->canvases[canvas_id].present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  *n_nodes = ctx->canvases[canvas_id].n_nodes;
+  return CVX_OK;
+}
+
+namespace {
+
+// The checks cvx_upload_pool makes on a leaf record.
+bool leaf_ok(const void* payloads, uint64_t i, uint32_t fmt) {
+  if (fmt == CVX_LEAF_RGBA8_F16) {
+    uint16_t h;
+    std::memcpy(&h, (const uint8_t*)payloads + i * 8 + 4, 2);
+    const bool negative = (h & 0x8000u) && (h & 0x7fffu);
+    const bool non_finite = (h & 0x7c00u) == 0x7c00u;
+    return !negative && !non_finite;
+  }
+  double v[4];
+  std::memcpy(v, (const uint8_t*)payloads + i * 32, 32);
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]) &&
+         std::isfinite(v[3]) && v[3] >= 0.0;
+}
+
+// Host mirror of the record words x, from the device records.
+int ensure_mirror(cvx_ctx* ctx, DevCanvas& c) {
+  if (c.mirror_ready) return CVX_OK;
+  c.mirror.assign(c.n_nodes, CVX_FREE);
+  uint32_t* packed = nullptr;
+  CVX_HIP(hipMalloc((void**)&packed, std::max<uint64_t>(c.n_nodes, 1) * 4));
+  int le = cvx::launch_extract_x(ctx->stream, c.rec, c.n_nodes, packed);
+  hipError_t e = (hipError_t)le;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c.mirror.data(), packed, c.n_nodes * 4, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(packed);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reading the pool records back");
+  c.leaves_at_depth.assign(64, 0);
+  c.n_refined = 0;
+  for (uint32_t x : c.mirror) {
+    if (x == CVX_FREE) continue;
+    if (x & 1u)
+      ++c.leaves_at_depth[(x >> 1) & 63u];
+    else
+      ++c.n_refined;
+  }
+  c.free_groups.clear();
+  c.mirror_ready = true;
+  return CVX_OK;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n_edits,
+                  const void* payloads, uint64_t n_payloads, uint32_t* first_child_out) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  DevCanvas& c = ctx->canvases[canvas_id];
+  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  if (n_edits && !edits) return fail(ctx, CVX_ERR_INVALID_ARG, "edits is NULL");
+  if (n_payloads && !payloads) return fail(ctx, CVX_ERR_INVALID_ARG, "payloads is NULL");
+  CVX_HIP(hipSetDevice(ctx->device));
+  int rc = ensure_mirror(ctx, c);
+  if (rc) return rc;
+  const uint32_t fmt = c.desc.leaf_format;
+  const uint32_t lb = leaf_bytes(fmt);
+
+  // ---- validate and apply to the mirror, with an undo log
+  std::vector<std::pair<uint32_t, uint32_t>> undo;  // (node, old x)
+  const std::vector<uint32_t> free0 = c.free_groups;
+  const std::vector<uint64_t> depth0 = c.leaves_at_depth;
+  const uint64_t refined0 = c.n_refined;
+  uint64_t n_cur = c.n_nodes;
+  std::vector<uint32_t> touched;                   // nodes whose record word changes
+  std::vector<std::pair<uint32_t, uint64_t>> paint;  // (node, payload index), in order
+  auto set_x = [&](uint32_t i, uint32_t x) {
+    undo.emplace_back(i, c.mirror[i]);
+    c.mirror[i] = x;
+    touched.push_back(i);
+  };
+  auto rollback = [&](int code, const std::string& m) {
+    for (size_t j = undo.size(); j-- > 0;) c.mirror[undo[j].first] = undo[j].second;
+    c.mirror.resize(c.n_nodes);
+    c.free_groups = free0;
+    c.leaves_at_depth = depth0;
+    c.n_refined = refined0;
+    return fail(ctx, code, m);
+  };
+  for (uint32_t e = 0; e < n_edits; ++e) {
+    const cvx_edit& ed = edits[e];
+    const std::string at = "edit " + std::to_string(e) + ": ";
+    if (first_child_out) first_child_out[e] = CVX_NONE_ID;
+    if (ed.node >= n_cur) return rollback(CVX_ERR_INVALID_ARG, at + "node out of range");
+    const uint32_t x = c.mirror[ed.node];
+    if (x == CVX_FREE) return rollback(CVX_ERR_INVALID_ARG, at + "node is not in the tree");
+    const bool leaf = (x & 1u) != 0;
+    const uint32_t np = ed.op == CVX_EDIT_REFINE ? 8u : 1u;
+    if (ed.op > CVX_EDIT_COARSEN) return rollback(CVX_ERR_INVALID_ARG, at + "unknown op");
+    if (ed.first_payload > n_payloads || n_payloads - ed.first_payload < np)
+      return rollback(CVX_ERR_INVALID_ARG, at + "payload index out of range");
+    for (uint32_t j = 0; j < np; ++j)
+      if (!leaf_ok(payloads, ed.first_payload + j, fmt))
+        return rollback(CVX_ERR_INVALID_ARG, at + "payload not finite or kappa < 0");
+    if (ed.op == CVX_EDIT_PAINT) {
+      if (!leaf) return rollback(CVX_ERR_INVALID_ARG, at + "PAINT needs a leaf");
+      paint.emplace_back(ed.node, ed.first_payload);
+    } else if (ed.op == CVX_EDIT_REFINE) {
+      if (!leaf) return rollback(CVX_ERR_INVALID_ARG, at + "REFINE needs a leaf");
+      const uint32_t d = (x >> 1) & 63u;
+      if (d + 1 > c.desc.max_depth)
+        return rollback(CVX_ERR_INVALID_ARG, at + "REFINE beyond the canvas max_depth");
+      uint64_t g;
+      if (!c.free_groups.empty()) {
+        g = c.free_groups.back();
+        c.free_groups.pop_back();
+      } else {
+        g = (n_cur + 7) & ~7ull;
+        if (g + 8 > (uint64_t)CVX_LEAF_BIT)
+          return rollback(CVX_ERR_INVALID_ARG, at + "pool would exceed 2^31 nodes");
+        c.mirror.resize(g + 8, CVX_FREE);
+        n_cur = g + 8;
+      }
+      set_x(ed.node, (uint32_t)g);
+      for (uint32_t o = 0; o < 8; ++o) {
+        set_x((uint32_t)g + o, 1u | ((d + 1) << 1));
+        paint.emplace_back((uint32_t)g + o, ed.first_payload + o);
+      }
+      --c.leaves_at_depth[d];
+      c.leaves_at_depth[d + 1] += 8;
+      ++c.n_refined;
+      if (first_child_out) first_child_out[e] = (uint32_t)g;
+    } else {
+      if (leaf) return rollback(CVX_ERR_INVALID_ARG, at + "COARSEN needs a refined node");
+      const uint32_t g = x;
+      uint32_t dc = 0;
+      for (uint32_t o = 0; o < 8; ++o) {
+        const uint32_t cx = c.mirror[g + o];
+        if (cx == CVX_FREE || !(cx & 1u))
+          return rollback(CVX_ERR_INVALID_ARG, at + "COARSEN needs 8 leaf children");
+        dc = (cx >> 1) & 63u;
+      }
+      set_x(ed.node, 1u | ((dc - 1) << 1));
+      for (uint32_t o = 0; o < 8; ++o) set_x(g + o, CVX_FREE);
+      c.free_groups.push_back(g);
+      c.leaves_at_depth[dc] -= 8;
+      ++c.leaves_at_depth[dc - 1];
+      --c.n_refined;
+      paint.emplace_back(ed.node, ed.first_payload);
+    }
+  }
+
+  // ---- device: grow, scatter records and payloads, rebuild G_3 and the table
+  auto device_fail = [&](hipError_t e, const char* where) {
+    // the device may be partly updated: mark the mirror stale so the next
+    // edit reads the device state back
+    c.mirror_ready = false;
+    c.mirror.clear();
+    return hip_fail(ctx, e, where);
+  };
+  if (n_cur > c.cap_nodes) {
+    uint64_t cap = std::max<uint64_t>(n_cur, std::min<uint64_t>(2 * c.cap_nodes, CVX_LEAF_BIT));
+    size_t free_b = 0, total_b = 0;
+    CVX_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (cap * (16 + lb) + (64ull << 20) > free_b) {
+      cap = n_cur;
+      if (cap * (16 + lb) + (64ull << 20) > free_b)
+        return rollback(CVX_ERR_OOM, "growing the pool needs more device memory");
+    }
+    void *nrec = nullptr, *npay = nullptr;
+    hipError_t e = hipMalloc(&nrec, cap * 16);
+    if (e == hipSuccess) e = hipMalloc(&npay, cap * lb);
+    if (e != hipSuccess) {
+      if (nrec) (void)hipFree(nrec);
+      return e == hipErrorOutOfMemory ? rollback(CVX_ERR_OOM, "device allocation failed")
+                                      : rollback(CVX_ERR_HIP, "hipMalloc while growing the pool");
+    }
+    e = hipMemsetAsync(nrec, 0xff, cap * 16, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(nrec, c.rec, c.n_nodes * 16, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(npay, c.pay, c.n_nodes * lb, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(nrec);
+      (void)hipFree(npay);
+      return device_fail(e, "growing the pool");
+    }
+    (void)hipFree(c.rec);
+    (void)hipFree(c.pay);
+    c.rec = nrec;
+    c.pay = npay;
+    c.bytes += (cap - c.cap_nodes) * (16 + lb);
+    c.cap_nodes = cap;
+  }
+  c.n_nodes = n_cur;
+
+  // last record word and last payload per node
+  std::sort(touched.begin(), touched.end());
+  touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+  std::vector<uint32_t> xs(touched.size());
+  for (size_t j = 0; j < touched.size(); ++j) xs[j] = c.mirror[touched[j]];
+  std::vector<std::pair<uint32_t, uint64_t>> last;
+  {
+    std::vector<std::pair<uint32_t, uint64_t>> tmp;
+    tmp.reserve(paint.size());
+    for (size_t j = 0; j < paint.size(); ++j) tmp.emplace_back(paint[j].first, j);
+    std::stable_sort(tmp.begin(), tmp.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (size_t j = 0; j < tmp.size(); ++j)
+      if (j + 1 == tmp.size() || tmp[j + 1].first != tmp[j].first)
+        last.emplace_back(tmp[j].first, paint[tmp[j].second].second);
+  }
+  std::vector<uint32_t> pay_ids(last.size());
+  std::vector<uint8_t> pay_src(last.size() * lb);
+  for (size_t j = 0; j < last.size(); ++j) {
+    pay_ids[j] = last[j].first;
+    std::memcpy(pay_src.data() + j * lb, (const uint8_t*)payloads + last[j].second * lb, lb);
+  }
+  const uint64_t n_internal = c.n_refined;
+  std::vector<uint32_t> roots;
+  const uint32_t R = c.desc.R, R3 = R * R * R;
+  for (uint32_t i = 0; i < R3; ++i)
+    if (!(c.mirror[i] & 1u)) roots.push_back(i);
+  uint32_t depth = 0;
+  for (uint32_t d = 0; d < 64; ++d)
+    if (c.leaves_at_depth[d]) depth = d;
+
+  DevBuf b_ids, b_xs, b_pids, b_psrc, b_order, b_count;
+  hipError_t e = hipSuccess;
+  const char* where = "";
+#define STEP(call)                      \
+  if (e == hipSuccess) {                \
+    e = (call);                         \
+    if (e != hipSuccess) where = #call; \
+  }
+  STEP(hipMalloc(&b_ids.p, std::max<size_t>(touched.size(), 1) * 4));
+  STEP(hipMalloc(&b_xs.p, std::max<size_t>(touched.size(), 1) * 4));
+  STEP(hipMalloc(&b_pids.p, std::max<size_t>(pay_ids.size(), 1) * 4));
+  STEP(hipMalloc(&b_psrc.p, std::max<size_t>(pay_src.size(), 8)));
+  STEP(hipMalloc(&b_order.p, std::max<uint64_t>(n_internal, 1) * 4));
+  STEP(hipMalloc(&b_count.p, 4));
+  if (e != hipSuccess) return device_fail(e, where);
+  if (!touched.empty()) {
+    STEP(hipMemcpyAsync(b_ids.p, touched.data(), touched.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    STEP(hipMemcpyAsync(b_xs.p, xs.data(), xs.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    if (e == hipSuccess) {
+      int le = cvx::launch_scatter_records(ctx->stream, (const uint32_t*)b_ids.p,
+                                           (const uint32_t*)b_xs.p, touched.size(), c.rec);
+      if (le != hipSuccess) { e = (hipError_t)le; where = "k_scatter_records"; }
+    }
+  }
+  if (!pay_ids.empty()) {
+    STEP(hipMemcpyAsync(b_pids.p, pay_ids.data(), pay_ids.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    STEP(hipMemcpyAsync(b_psrc.p, pay_src.data(), pay_src.size(), hipMemcpyHostToDevice, ctx->stream));
+    if (e == hipSuccess) {
+      int le = cvx::launch_scatter_payloads(ctx->stream, (const uint32_t*)b_pids.p, b_psrc.p,
+                                            pay_ids.size(), lb, c.pay);
+      if (le != hipSuccess) { e = (hipError_t)le; where = "k_scatter_payloads"; }
+    }
+  }
+  // G_3, level by level from the refined roots (their links are the root
+  // array's and never change)
+  if (!roots.empty())
+    STEP(hipMemcpyAsync(b_order.p, roots.data(), roots.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  uint64_t lo = 0, hi = roots.size();
+  for (uint32_t level = 0; e == hipSuccess && hi > lo; ++level) {
+    const uint32_t h32 = (uint32_t)hi;
+    STEP(hipMemcpyAsync(b_count.p, &h32, 4, hipMemcpyHostToDevice, ctx->stream));
+    if (e != hipSuccess) break;
+    int le = cvx::launch_links_level(ctx->stream, (const uint32_t*)b_order.p + lo, hi - lo, level,
+                                     c.rec, R, (uint32_t*)b_order.p, (uint32_t*)b_count.p,
+                                     c.n_nodes);
+    if (le != hipSuccess) { e = (hipError_t)le; where = "k_links_level"; break; }
+    uint32_t cnt = 0;
+    STEP(hipMemcpyAsync(&cnt, b_count.p, 4, hipMemcpyDeviceToHost, ctx->stream));
+    STEP(hipStreamSynchronize(ctx->stream));
+    if (e != hipSuccess) break;
+    if (cnt > n_internal) { e = hipErrorUnknown; where = "G_3 rebuild frontier overflow"; break; }
+    lo = hi;
+    hi = cnt;
+  }
+  // top-level table for the new depth
+  const uint32_t L = cvx::top_table_depth(R, depth);
+  if (e == hipSuccess && L != c.top_depth) {
+    if (c.top) (void)hipFree(c.top);
+    c.top = nullptr;
+    c.top_depth = 0;
+    if (L) {
+      const uint64_t side = (uint64_t)R << L;
+      STEP(hipMalloc((void**)&c.top, side * side * side * 4));
+      if (e == hipSuccess) c.top_depth = L;
+    }
+  }
+  if (e == hipSuccess && c.top_depth) {
+    int le = cvx::launch_top_table(ctx->stream, c.rec, c.n_nodes, R, c.top_depth, c.top);
+    if (le != hipSuccess) { e = (hipError_t)le; where = "k_top_table"; }
+  }
+  STEP(hipStreamSynchronize(ctx->stream));
+#undef STEP
+  if (e != hipSuccess) return device_fail(e, where);
+  c.depth = depth;
   return CVX_OK;
 }
 

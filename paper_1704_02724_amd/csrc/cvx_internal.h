@@ -9,6 +9,7 @@
 
 #define CVX_LEAF_BIT 0x80000000u
 #define CVX_NONE 0xffffffffu
+#define CVX_FREE 0xffffffffu  // record word x of a node that is not in the tree
 
 namespace cvx {
 
@@ -41,6 +42,15 @@ struct DevCanvas {
   uint32_t* top = nullptr;  // top-level table: node covering each cell of depth top_depth
   uint32_t top_depth = 0;   // 0: no table
   uint64_t bytes = 0;
+  // pool edits: device capacity in nodes, and a host mirror of every record
+  // word x (built on the first edit), the freed groups (LIFO) and the leaf
+  // count per depth
+  uint64_t cap_nodes = 0;
+  bool mirror_ready = false;
+  std::vector<uint32_t> mirror;
+  std::vector<uint32_t> free_groups;
+  std::vector<uint64_t> leaves_at_depth;
+  uint64_t n_refined = 0;  // refined nodes in the tree
 };
 
 // Depth of the top-level table of a canvas: at most 6 levels and 2^18 cells,
@@ -112,6 +122,14 @@ struct CastArgs {
 // kernel launchers (cvx_upload.hip, cvx_cast.hip); return a hipError_t value
 int launch_top_table(void* stream, const void* rec, uint64_t n_nodes, uint32_t R, uint32_t L,
                      uint32_t* top);
+int launch_extract_x(void* stream, const void* rec, uint64_t n, uint32_t* out);
+int launch_scatter_records(void* stream, const uint32_t* ids, const uint32_t* xs, uint64_t n,
+                           void* rec);
+int launch_scatter_payloads(void* stream, const uint32_t* ids, const void* src, uint64_t n,
+                            uint32_t leaf_bytes, void* pay);
+int launch_links_level(void* stream, const uint32_t* frontier, uint64_t n, uint32_t level,
+                       void* rec, uint32_t R, uint32_t* next, uint32_t* next_count,
+                       uint64_t n_nodes);
 int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, uint64_t end,
                           uint32_t level, const void* raw_nodes, const void* raw_leaves,
                           uint32_t fmt, void* rec, void* pay, uint32_t R);

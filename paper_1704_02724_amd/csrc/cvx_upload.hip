@@ -19,7 +19,7 @@
 
 namespace cvx {
 
-__device__ __forceinline__ uint32_t neighbour_of_parent(const uint4* __restrict__ rec, uint32_t P,
+__device__ __forceinline__ uint32_t neighbour_of_parent(const uint4* rec, uint32_t P,
                                                         uint32_t plevel, uint32_t k, uint32_t s,
                                                         uint32_t R) {
   if (plevel == 0) {
@@ -103,6 +103,100 @@ int launch_top_table(void* stream, const void* rec, uint64_t n_nodes, uint32_t R
   const uint32_t bs = 256;
   hipLaunchKernelGGL(k_top_table, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
                      (hipStream_t)stream, (const uint4*)rec, n_nodes, R, L, top);
+  return (int)hipGetLastError();
+}
+
+// ---- pool edits -------------------------------------------------------------
+// Record words x of nodes [0, n), packed (for the host mirror).
+__global__ void k_extract_x(const uint4* __restrict__ rec, uint64_t n, uint32_t* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = rec[i].x;
+}
+
+int launch_extract_x(void* stream, const void* rec, uint64_t n, uint32_t* out) {
+  if (!n) return hipSuccess;
+  const uint32_t bs = 256;
+  hipLaunchKernelGGL(k_extract_x, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, (const uint4*)rec, n, out);
+  return (int)hipGetLastError();
+}
+
+// Record words x of touched nodes (first child, 1 | depth << 1, or CVX_FREE).
+__global__ void k_scatter_records(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ xs,
+                                  uint64_t n, uint4* __restrict__ rec) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint4 r = make_uint4(xs[i], CVX_NONE, CVX_NONE, CVX_NONE);
+  rec[ids[i]] = r;
+}
+
+// Payloads of touched leaves, lb bytes each (8 or 32, so whole uint2 words).
+__global__ void k_scatter_payloads(const uint32_t* __restrict__ ids, const uint2* __restrict__ src,
+                                   uint64_t n, uint32_t words, uint2* __restrict__ pay) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * words) return;
+  const uint64_t j = i / words, w = i % words;
+  pay[(uint64_t)ids[j] * words + w] = src[i];
+}
+
+// One level of the G_3 rebuild: for every refined node P of the frontier
+// (depth `level`, links already final), derive the outer links of its 8
+// children as at upload and append the refined children to the next
+// frontier.  Only the children's y, z, w words are written; the x words and
+// the links of level `level` are read.
+__global__ void k_links_level(const uint32_t* __restrict__ frontier, uint64_t n, uint32_t level,
+                              uint4* rec, uint32_t R, uint32_t* __restrict__ next,
+                              uint32_t* __restrict__ next_count, uint64_t n_nodes) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t P = frontier[i];
+  const uint32_t first = rec[P].x;
+  if ((first & 1u) || (uint64_t)first + 8 > n_nodes) return;
+  for (uint32_t o = 0; o < 8; ++o) {
+    const uint32_t C = first + o;
+    uint32_t link[3];
+    for (uint32_t k = 0; k < 3; ++k) {
+      uint32_t M = neighbour_of_parent(rec, P, level, k, (o >> k) & 1u, R);
+      if (M != CVX_NONE) {
+        const uint32_t mx = rec[M].x;
+        if (!(mx & 1u)) M = mx + (o ^ (1u << k));
+      }
+      link[k] = M;
+    }
+    uint32_t* w = (uint32_t*)&rec[C];
+    w[1] = link[0];
+    w[2] = link[1];
+    w[3] = link[2];
+    if (!(rec[C].x & 1u)) next[atomicAdd(next_count, 1u)] = C;
+  }
+}
+
+int launch_scatter_records(void* stream, const uint32_t* ids, const uint32_t* xs, uint64_t n,
+                           void* rec) {
+  if (!n) return hipSuccess;
+  const uint32_t bs = 256;
+  hipLaunchKernelGGL(k_scatter_records, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, ids, xs, n, (uint4*)rec);
+  return (int)hipGetLastError();
+}
+
+int launch_scatter_payloads(void* stream, const uint32_t* ids, const void* src, uint64_t n,
+                            uint32_t leaf_bytes, void* pay) {
+  if (!n) return hipSuccess;
+  const uint32_t bs = 256, words = leaf_bytes / 8;
+  hipLaunchKernelGGL(k_scatter_payloads, dim3((uint32_t)((n * words + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, ids, (const uint2*)src, n, words, (uint2*)pay);
+  return (int)hipGetLastError();
+}
+
+int launch_links_level(void* stream, const uint32_t* frontier, uint64_t n, uint32_t level,
+                       void* rec, uint32_t R, uint32_t* next, uint32_t* next_count,
+                       uint64_t n_nodes) {
+  if (!n) return hipSuccess;
+  const uint32_t bs = 256;
+  hipLaunchKernelGGL(k_links_level, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, frontier, n, level, (uint4*)rec, R, next, next_count,
+                     n_nodes);
   return (int)hipGetLastError();
 }
 

@@ -43,7 +43,12 @@ CVX_STAT_COUNT = 8
 
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",
             "cvx_last_error", "cvx_status_str", "cvx_validate_pool", "cvx_validate_views",
-            "cvx_pool_bytes", "cvx_autotune"]
+            "cvx_pool_bytes", "cvx_autotune", "cvx_edit_pool", "cvx_pool_nodes"]
+
+CVX_EDIT_PAINT = 0
+CVX_EDIT_REFINE = 1
+CVX_EDIT_COARSEN = 2
+CVX_NONE_ID = 0xFFFFFFFF
 
 
 class cvx_canvas_desc(ctypes.Structure):
@@ -75,6 +80,11 @@ class cvx_render_opts(ctypes.Structure):
                 ("out_f64", ctypes.c_uint32), ("top_lookup", ctypes.c_uint32),
                 ("single_queue", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
+
+
+class cvx_edit(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("node", ctypes.c_uint32),
+                ("first_payload", ctypes.c_uint64)]
 
 
 class cvx_tune_result(ctypes.Structure):
@@ -110,6 +120,8 @@ _lib.cvx_validate_pool.argtypes = [ctypes.POINTER(cvx_canvas_desc), _vp, ctypes.
 _lib.cvx_validate_views.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_char_p,
                                     ctypes.c_size_t]
 _lib.cvx_pool_bytes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+_lib.cvx_edit_pool.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, ctypes.c_uint64, _vp]
+_lib.cvx_pool_nodes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
 _lib.cvx_autotune.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(cvx_render_opts),
                               ctypes.c_uint32, ctypes.POINTER(cvx_render_opts),
                               ctypes.POINTER(cvx_tune_result), ctypes.c_uint32,
@@ -193,6 +205,28 @@ def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
     rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms), r.top_lookup,
              r.single_queue) for r in res[:min(n.value, max_results)]]
     return best, rows
+
+
+def cvx_edit_pool(ctx, canvas_id, edits, payloads):
+    """edits: sequence of (op, node, first_payload); payloads: leaf records in the
+    pool's format (numpy structured array).  Returns the first child id per edit
+    (CVX_NONE_ID for edits that are not REFINE)."""
+    n = len(edits)
+    arr = (cvx_edit * max(n, 1))()
+    for i, (op, node, fp) in enumerate(edits):
+        arr[i].op, arr[i].node, arr[i].first_payload = int(op), int(node), int(fp)
+    payloads = np.ascontiguousarray(payloads)
+    out = np.full(max(n, 1), CVX_NONE_ID, np.uint32)
+    _check(ctx, _lib.cvx_edit_pool(ctx, int(canvas_id), ctypes.cast(arr, _vp), n,
+                                   payloads.ctypes.data if len(payloads) else None, len(payloads),
+                                   out.ctypes.data))
+    return out[:n]
+
+
+def cvx_pool_nodes(ctx, canvas_id) -> int:
+    b = ctypes.c_uint64()
+    _check(ctx, _lib.cvx_pool_nodes(ctx, int(canvas_id), ctypes.byref(b)))
+    return int(b.value)
 
 
 def cvx_free_pool(ctx, canvas_id):

@@ -44,6 +44,11 @@ class Session:
         cvx.cvx_upload_pool(self.ctx, canvas_id, d, canvas.nodes, canvas.leaves)
         self.descs[canvas_id] = d
 
+    def edit(self, canvas_id, edits, payloads):
+        """Apply pool edits (cvx_edit_pool); returns the first child id per edit."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return cvx.cvx_edit_pool(self.ctx, canvas_id, edits, payloads)
+
     def free(self, canvas_id):
         cvx.cvx_free_pool(self.ctx, canvas_id)
         self.descs.pop(canvas_id, None)
