@@ -57,6 +57,8 @@ extern "C" {
 #define CVX_VARIANT_FP32_REBASED 0u /* FP32 cell-local traversal, FP64 rebase */
 #define CVX_VARIANT_FP64_PLAIN 1u   /* FP64 canvas-global traversal and compositing */
 #define CVX_VARIANT_FP32_NAIVE 2u   /* FP32 canvas-global traversal (drifts at depth) */
+#define CVX_VARIANT_FP32_CELL_LOCAL 3u /* the paper's uncertified FP32 cell-local traversal
+                                          (Sec. 6.2), for the precision experiment */
 
 #define CVX_MAX_CANVASES 64
 #define CVX_MAX_DEPTH 30
@@ -127,6 +129,8 @@ typedef struct {
   uint32_t* n_leaves;      /* n: total segments (may exceed max_leaves) */
   uint32_t* flags;         /* n: CVX_RAYFLAG_* */
   float* rgba;             /* 4n */
+  double* end_point;       /* 3n, may be NULL: exit point of the last leaf as the variant
+                              computed it, canvas units (root edge 1, canvas corner 0) */
 } cvx_trace;
 
 /* Render options.  Zero means "default" for every tuning field. */

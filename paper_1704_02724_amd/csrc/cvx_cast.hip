@@ -21,6 +21,8 @@
 //                step, FP64 compositing.  The GPU baseline.
 //  FP32_NAIVE    canvas-global FP32 (the paper's "canvas coordinate"
 //                traversal that drifts at depth); kept to show the failure.
+//  FP32_CELL_LOCAL  the paper's own cell-local FP32 traversal (Sec. 6.2),
+//                uncertified; the subject of its error analysis (Sec. 6.3).
 #include <hip/hip_runtime.h>
 
 #include "cvx_internal.h"
@@ -59,6 +61,7 @@ struct Acc {
 
 struct Out {
   double rgba[4];
+  double end[3];   // trace mode: the exit point of the last leaf as the variant computed it
   uint32_t flags;
   uint32_t n;
   uint32_t steps;  // loop iterations of this ray
@@ -391,7 +394,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
   // current cell I is descended first when it is refined.
   bool bad = false;  // a node index outside the pool (never for a validated pool)
+  double te_last = 0.0;  // trace mode: ray parameter of the last rebase
   auto rebase = [&](double te) __attribute__((always_inline)) {
+    if (TRACE) te_last = te;
     const uint32_t d0 = dep;
     bad = bad || !descend_int(rec, v.n_nodes, deep_coords(q, up, v.R, v.max_depth), v.max_depth,
                               I, dep, c, r);
@@ -503,6 +508,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       }
       const float Sx = get(S, kx);
       const float ex = get(eb, kx);
+      if (TRACE) {
+        const double t = te_last + ldexp((double)Sx, -(int)db);
+        for (int k = 0; k < 3; ++k) out.end[k] = slot.at(k) + t * slot.at(3 + k);
+      }
       // length precision guard: rebase once the bound on this segment's
       // length exceeds 2^-10 of the leaf edge (w base cells)
       need64 = need64 || (ex + e_ent > 0x1p-10f * (float)w);
@@ -634,6 +643,8 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
     }
     double len = ldexp(best - t_ent, (int)dep);
     len = len > 0.0 ? len : 0.0;
+    if (TRACE)
+      for (int k = 0; k < 3; ++k) out.end[k] = get(o, k) + best * get(d, k);
     double cr, cg, cb, kap;
     if (v.fmt == CVX_LEAF_F64) {
       const double4 p = ((const double4*)v.pay)[I];
@@ -731,6 +742,9 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
     }
     float len = (best - t_ent) * ldexpf(1.0f, (int)dep);
     len = len > 0.0f ? len : 0.0f;
+    if (TRACE)
+      for (int k = 0; k < 3; ++k)
+        out.end[k] = k == kx ? (double)Xb : (double)(get(of, k) + best * get(df, k));
     const uint2 pay = ld_pay(payp, I);
     const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * len * -1.4426950408889634f);
     const float a = T - Tn;
@@ -774,6 +788,131 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
   if (STATS) acc.leaves += n_rec;
 }
 
+// ----------------------------------------------------------------------------
+// FP32_CELL_LOCAL: the paper's traversal (Sec. 6.2).  The entry point p of the
+// current leaf is held in the leaf's own frame (origin at its centre, edge 1)
+// in FP32; the exit face is the argmin of t_k = (+-0.5 - p_k) / d_k, the exit
+// point p' = p + t d, and p' is mapped into the next cell by a power-of-two
+// scale and a shift (across a face: shift by one edge on that axis; into a
+// coarser leaf: scale by 2^-m after the integer offset of the finer cell; into
+// a refined cell: child by the sign of p, then p -> 2p - b + 1/2 per level).
+// The start point is the only FP64 step (rounded once into the first leaf's
+// frame).  Nothing is certified: this is the scheme whose error Sec. 6.3
+// bounds, measured by the precision experiment.
+// ----------------------------------------------------------------------------
+template <bool TRACE, bool STATS>
+__device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
+                           Sink sk, Acc& acc, Out& out) {
+  const V3<double> o{v.o[0], v.o[1], v.o[2]};
+  const double Rd = (double)v.R;
+  const void* rec = v.rec;
+  const void* payp = v.pay;
+  const bool use_stop = v.alpha_stop < 1.0f;
+  const V3<float> df{(float)d.x, (float)d.y, (float)d.z};
+  V3<double> q;
+  for (int k = 0; k < 3; ++k) {
+    double qk = get(o, k) + en.t0 * get(d, k);
+    if (k == en.kin) qk = en.side ? Rd : 0.0;
+    set(q, k, qk < 0.0 ? 0.0 : (qk > Rd ? Rd : qk));
+  }
+  uint32_t I, dep = 0;
+  V3<uint32_t> c;
+  uint4 r;
+  const V3<uint32_t> C0 = deep_coords(q, up, v.R, v.max_depth);
+  locate_top(v, C0, I, dep, c, r);
+  bool bad = !descend_int(rec, v.n_nodes, C0, v.max_depth, I, dep, c, r);
+  if (STATS) acc.descent += dep;
+  V3<float> p;
+  for (int k = 0; k < 3; ++k)
+    set(p, k, (float)(ldexp(get(q, k), (int)dep) - (double)get(c, k) - 0.5));
+  float T = 1.0f;
+  V3<float> C{0.f, 0.f, 0.f};
+  uint32_t n_rec = 0;
+  uint32_t step = 0;
+  for (;; ++step) {
+    if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
+    if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
+    float best = BIGF;
+    int kx = 0;
+    for (int k = 0; k < 3; ++k) {
+      const float face = get(up, k) ? 0.5f : -0.5f;
+      const float tt = get(df, k) == 0.0f ? BIGF : (face - get(p, k)) / get(df, k);
+      kx = tt < best ? k : kx;
+      best = tt < best ? tt : best;
+    }
+    const float len = best > 0.0f ? best : 0.0f;   // leaf edges
+    V3<float> pe;
+    for (int k = 0; k < 3; ++k) set(pe, k, __builtin_fmaf(len, get(df, k), get(p, k)));
+    if (TRACE) {
+      const double h = ldexp(1.0, -(int)dep);
+      for (int k = 0; k < 3; ++k)
+        out.end[k] = ((double)get(c, k) + 0.5 + (double)get(pe, k)) * h;
+    }
+    const uint2 pay = ld_pay(payp, I);
+    const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * len * -1.4426950408889634f);
+    const float a = T - Tn;
+    C.x = __builtin_fmaf(a, (float)(pay.x & 0xffu), C.x);
+    C.y = __builtin_fmaf(a, (float)((pay.x >> 8) & 0xffu), C.y);
+    C.z = __builtin_fmaf(a, (float)((pay.x >> 16) & 0xffu), C.z);
+    T = Tn;
+    if (TRACE) record(sk, n_rec, I, len);
+    ++n_rec;
+    const uint32_t ck = get(c, kx);
+    const bool upk = get(up, kx);
+    const Move mv = neighbour(v, I, r, dep, ck, upk, kx);
+    if (mv.at_edge || mv.N >= v.n_nodes || (use_stop && 1.0f - T >= v.alpha_stop)) {
+      if (!mv.at_edge && mv.N >= v.n_nodes) out.flags |= CVX_RAYFLAG_BAD_LINK;
+      break;
+    }
+    if (STATS) acc.outer += mv.outer;
+    // across the face: one edge along kx
+    p = pe;
+    set(p, kx, get(pe, kx) - (upk ? 1.0f : -1.0f));
+    set(c, kx, mv.nc);
+    I = mv.N;
+    r = ld_rec(rec, I);
+    if (r.x & 1u) {
+      // a coarser leaf: scale by 2^-m after the offset of the finer cell in it
+      const uint32_t dL = (r.x >> 1) & 63u;
+      const uint32_t m = dL < dep ? dep - dL : 0u;
+      const float sc = ldexpf(1.0f, -(int)m);
+      const uint32_t mask = (1u << m) - 1u;
+      for (int k = 0; k < 3; ++k) {
+        const float off = (float)(get(c, k) & mask);
+        set(p, k, __builtin_fmaf(get(p, k) + 0.5f + off, sc, -0.5f));
+        set(c, k, get(c, k) >> m);
+      }
+      dep -= m;
+    } else {
+      // a refined cell: children by the sign of p, ties to the side the ray moves into
+      const uint32_t d0 = dep;
+      while (!(r.x & 1u)) {
+        if (r.x >= v.n_nodes - 7u) { bad = true; break; }
+        uint32_t oct = 0;
+        for (int k = 0; k < 3; ++k) {
+          const float pk = get(p, k);
+          const uint32_t b = (pk > 0.0f || (pk == 0.0f && get(up, k))) ? 1u : 0u;
+          oct |= b << k;
+          set(p, k, 2.0f * pk - (float)b + 0.5f);
+          set(c, k, 2u * get(c, k) + b);
+        }
+        I = r.x + oct;
+        ++dep;
+        r = ld_rec(rec, I);
+      }
+      if (STATS) acc.descent += dep - d0;
+    }
+  }
+  const float k255 = 1.0f / 255.0f;
+  out.rgba[0] = C.x * k255;
+  out.rgba[1] = C.y * k255;
+  out.rgba[2] = C.z * k255;
+  out.rgba[3] = 1.0f - T;
+  out.n = n_rec;
+  out.steps = step + 1;
+  if (STATS) acc.leaves += n_rec;
+}
+
 template <int VAR, bool TRACE, bool STATS>
 __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out) {
   const RaySlot slot{(lds_f64*)(s_ray + threadIdx.x), blockDim.x};
@@ -783,6 +922,7 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   out.flags = 0;
   out.n = 0;
   out.steps = 0;
+  out.end[0] = out.end[1] = out.end[2] = 0.0;
   if (STATS) acc.rays++;
   const Entry en = canvas_entry(o, d, (double)v.R);
   if (!en.hit) return;
@@ -791,8 +931,10 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
     cast_fp32<TRACE, STATS>(v, slot, o, d, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
     cast_fp64<TRACE, STATS>(v, d, en, up, sk, acc, out);
-  } else {
+  } else if constexpr (VAR == (int)CVX_VARIANT_FP32_NAIVE) {
     cast_naive<TRACE, STATS>(v, d, en, up, sk, acc, out);
+  } else {
+    cast_local<TRACE, STATS>(v, d, en, up, sk, acc, out);
   }
 }
 
@@ -872,6 +1014,8 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
             cast_ray<VAR, TRACE, STATS>(v, pix % v.W, pix / v.W, sk, acc, res);
             a.n_leaves[ri] = res.n;
             a.flags[ri] = res.flags;
+            if (a.end_point)
+              for (int k = 0; k < 3; ++k) a.end_point[3 * ri + k] = res.end[k];
             ((float4*)a.trace_rgba)[ri] = make_float4((float)res.rgba[0], (float)res.rgba[1],
                                                       (float)res.rgba[2], (float)res.rgba[3]);
           }
@@ -967,6 +1111,9 @@ int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out
     case CVX_VARIANT_FP32_NAIVE:
       return launch_v<(int)CVX_VARIANT_FP32_NAIVE>(stream, trace, stats, false, a, workgroups,
                                                    wg_size);
+    case CVX_VARIANT_FP32_CELL_LOCAL:
+      return launch_v<(int)CVX_VARIANT_FP32_CELL_LOCAL>(stream, trace, stats, false, a,
+                                                        workgroups, wg_size);
     default:
       return (int)hipErrorInvalidValue;
   }

@@ -115,6 +115,7 @@ struct CastArgs {
   uint32_t* n_leaves;
   uint32_t* flags;
   float* trace_rgba;
+  double* end_point;
   uint64_t* stats;
   uint32_t tile_w, tile_h;
 };

@@ -32,7 +32,8 @@ CVX_LEAF_F64 = 1
 CVX_VARIANT_FP32_REBASED = 0
 CVX_VARIANT_FP64_PLAIN = 1
 CVX_VARIANT_FP32_NAIVE = 2
-VARIANTS = {"fp32_rebased": 0, "fp64_plain": 1, "fp32_naive": 2}
+CVX_VARIANT_FP32_CELL_LOCAL = 3
+VARIANTS = {"fp32_rebased": 0, "fp64_plain": 1, "fp32_naive": 2, "fp32_cell_local": 3}
 
 CVX_RAYFLAG_STEP_CAP = 1
 CVX_RAYFLAG_FP64_EXIT = 2
@@ -70,7 +71,8 @@ class cvx_trace(ctypes.Structure):
                 ("max_leaves", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("leaf_ids", ctypes.c_void_p), ("local_len", ctypes.c_void_p),
                 ("local_len64", ctypes.c_void_p), ("n_leaves", ctypes.c_void_p),
-                ("flags", ctypes.c_void_p), ("rgba", ctypes.c_void_p)]
+                ("flags", ctypes.c_void_p), ("rgba", ctypes.c_void_p),
+                ("end_point", ctypes.c_void_p)]
 
 
 class cvx_render_opts(ctypes.Structure):

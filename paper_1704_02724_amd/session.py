@@ -101,7 +101,8 @@ class Session:
     def new_stats(self):
         return self.torch.zeros(cvx.CVX_STAT_COUNT, dtype=self.torch.int64, device=self.device)
 
-    def trace(self, views, ray_ids, max_leaves=256, variant="fp32_rebased", len64=False):
+    def trace(self, views, ray_ids, max_leaves=256, variant="fp32_rebased", len64=False,
+              end_point=False):
         torch = self.torch
         ids = torch.from_numpy(np.ascontiguousarray(ray_ids, dtype=np.uint64).view(np.int64))
         ids = ids.to(self.device)
@@ -112,6 +113,7 @@ class Session:
         nl = torch.zeros(n, dtype=torch.int32, device=self.device)
         fl = torch.zeros(n, dtype=torch.int32, device=self.device)
         rgba = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
+        end = torch.zeros((n, 3), dtype=torch.float64, device=self.device) if end_point else None
         tr = cvx.cvx_trace()
         tr.n = n
         tr.ray_ids = ids.data_ptr()
@@ -122,12 +124,16 @@ class Session:
         tr.n_leaves = nl.data_ptr()
         tr.flags = fl.data_ptr()
         tr.rgba = rgba.data_ptr()
+        tr.end_point = end.data_ptr() if end is not None else None
         varr = cvx.make_views(views)
         opts = cvx.make_opts(variant, trace=tr)
         self._enter()
         cvx.cvx_render(self.ctx, varr, 0, opts)
-        self._leave(ids, leaf_ids, llen, nl, fl, rgba)
+        self._leave(ids, leaf_ids, llen, nl, fl, rgba, *([end] if end is not None else []))
         torch.cuda.synchronize(self.device)
-        return dict(leaf_ids=leaf_ids.cpu().numpy().view(np.uint32), local_len=llen.cpu().numpy(),
-                    n_leaves=nl.cpu().numpy().view(np.uint32), flags=fl.cpu().numpy().view(np.uint32),
-                    rgba=rgba.cpu().numpy())
+        res = dict(leaf_ids=leaf_ids.cpu().numpy().view(np.uint32), local_len=llen.cpu().numpy(),
+                   n_leaves=nl.cpu().numpy().view(np.uint32), flags=fl.cpu().numpy().view(np.uint32),
+                   rgba=rgba.cpu().numpy())
+        if end is not None:
+            res["end_point"] = end.cpu().numpy()
+        return res
