@@ -126,53 +126,73 @@ def time_per_view(sess, views, variant, steps, tuning):
 
 
 def edit_bench(sess, cv, n_paint, n_refine, n_coarsen, seed):
-    """Times cvx_edit_pool on a second copy of the canvas: one batch of paints,
-    refinements and coarsenings on disjoint nodes (the first call also builds the
-    host mirror of the pool), against a full cvx_upload_pool."""
+    """Times cvx_edit_pool on a second copy of the canvas against a full
+    cvx_upload_pool: two batches of paints, refinements and coarsenings on
+    disjoint nodes, the first of which grows the pool (new capacity, the visit
+    marks of the link rebuild) and the second of which refines into the groups
+    the first one freed.  A single paint before them builds the host mirror."""
     from canvasgen.pool import LEAF, LEAF_DTYPE
+    from paper_1704_02724_amd.cvx import EDIT_DTYPE
     torch = sess.torch
     rng = np.random.Generator(np.random.PCG64(seed))
     child = cv.nodes[:, 0]
     is_leaf = (child & LEAF) != 0
     internal = np.nonzero(~is_leaf)[0]
-    internal = internal[internal >= 0]
     kids = child[internal][:, None].astype(np.int64) + np.arange(8)[None, :]
     ok = np.all(is_leaf[kids], axis=1)
-    coarse = rng.permutation(internal[ok])[:n_coarsen]
+    coarse = rng.permutation(internal[ok])[:2 * n_coarsen]
     busy = np.zeros(len(child), bool)
     busy[(child[coarse][:, None].astype(np.int64) + np.arange(8)[None, :]).ravel()] = True
     # leaves in the tree: the padding slots after the roots have no parent
     in_tree = (cv.nodes[:, 1] != 0xFFFFFFFF) | (np.arange(len(child)) < cv.R ** 3)
     cand = np.nonzero(is_leaf & ~busy & in_tree)[0]
-    pick = rng.permutation(cand)[:n_paint + n_refine]
-    paint, refine = pick[:n_paint], pick[n_paint:]
-    pays = np.zeros(n_paint + 8 * n_refine + n_coarsen, LEAF_DTYPE[cv.leaf_format])
+    pick = rng.permutation(cand)[:2 * (n_paint + n_refine) + 1]
+    n_pay = n_paint + 8 * n_refine + n_coarsen
+    pays = np.zeros(n_pay, LEAF_DTYPE[cv.leaf_format])
     if cv.leaf_format == 0:
-        pays["r"], pays["g"], pays["b"] = (rng.integers(0, 256, (3, len(pays)))).astype(np.uint8)
+        pays["r"], pays["g"], pays["b"] = (rng.integers(0, 256, (3, n_pay))).astype(np.uint8)
         pays["kappa"] = np.float16(0.5).view(np.uint16)
     else:
         pays["kappa"] = 0.5
-    edits = ([(0, int(n), i) for i, n in enumerate(paint)]
-             + [(1, int(n), n_paint + 8 * i) for i, n in enumerate(refine)]
-             + [(2, int(n), n_paint + 8 * n_refine + i) for i, n in enumerate(coarse)])
+
+    def batch(k):
+        paint = pick[k * (n_paint + n_refine):][:n_paint]
+        refine = pick[k * (n_paint + n_refine) + n_paint:][:n_refine]
+        co = coarse[k * n_coarsen:][:n_coarsen]
+        ed = np.zeros(len(paint) + len(refine) + len(co), EDIT_DTYPE)
+        a, b = len(paint), len(paint) + len(refine)
+        ed["op"][:a], ed["op"][a:b], ed["op"][b:] = 0, 1, 2
+        ed["node"] = np.concatenate([paint, refine, co]).astype(np.uint32)
+        ed["first_payload"][:a] = np.arange(a)
+        ed["first_payload"][a:b] = n_paint + 8 * np.arange(b - a)
+        ed["first_payload"][b:] = n_paint + 8 * n_refine + np.arange(len(ed) - b)
+        return ed
+
+    batches = [batch(0), batch(1)]
+    first = np.zeros(1, EDIT_DTYPE)
+    first["node"] = pick[-1]
     torch.cuda.synchronize()
-    log(f"pool edits: {len(edits)} edits drawn")
+    log(f"pool edits: 2 x {len(batches[0])} edits drawn")
     t = time.perf_counter()
     sess.upload(9, cv)
     torch.cuda.synchronize()
     upload_ms = (time.perf_counter() - t) * 1e3
     log(f"pool edits: upload of the copy {upload_ms:.1f} ms")
     t = time.perf_counter()
-    sess.edit(9, [(0, int(paint[0]), 0)], pays[:1])       # builds the host mirror
+    sess.edit(9, first, pays)                             # builds the host mirror
     first_ms = (time.perf_counter() - t) * 1e3
     log(f"pool edits: first edit (mirror build) {first_ms:.1f} ms")
-    t = time.perf_counter()
-    sess.edit(9, edits, pays)
-    edit_ms = (time.perf_counter() - t) * 1e3
+    ms = []
+    for ed in batches:
+        t = time.perf_counter()
+        sess.edit(9, ed, pays)
+        ms.append((time.perf_counter() - t) * 1e3)
+        log(f"pool edits: batch of {len(ed)} edits {ms[-1]:.1f} ms")
     sess.free(9)
-    return dict(paint=int(len(paint)), refine=int(len(refine)), coarsen=int(len(coarse)),
-                edit_ms=round(edit_ms, 2), first_edit_ms=round(first_ms, 2),
-                upload_ms=round(upload_ms, 2), nodes=int(cv.n_nodes))
+    return dict(paint=int(n_paint), refine=int(n_refine), coarsen=int(n_coarsen),
+                edit_ms_growing=round(ms[0], 2), edit_ms=round(ms[1], 2),
+                first_edit_ms=round(first_ms, 2), upload_ms=round(upload_ms, 2),
+                nodes=int(cv.n_nodes))
 
 
 def main():

@@ -253,6 +253,13 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
 /* Number of node ids of the pool under canvas_id (including freed groups). */
 int cvx_pool_nodes(cvx_ctx* ctx, int canvas_id, uint64_t* n_nodes);
 
+/* Diagnostic copy of device node records [first, first + count) into the host
+ * array out (4 uint32 per node): x = first child, or 1 | depth << 1 for a
+ * leaf, or 0xffffffff for an id not in the tree; then the outer-face
+ * neighbours on the x, y, z axes (0xffffffff for none).  Synchronous;
+ * CVX_ERR_INVALID_ARG if the range passes the pool's node count. */
+int cvx_read_records(cvx_ctx* ctx, int canvas_id, uint64_t first, uint64_t count, uint32_t* out);
+
 /* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
 int cvx_free_pool(cvx_ctx* ctx, int canvas_id);
 

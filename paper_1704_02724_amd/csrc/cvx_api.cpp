@@ -4,8 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "cvx_internal.h"
@@ -68,6 +70,7 @@ void free_canvas(DevCanvas& c) {
   if (c.rec) (void)hipFree(c.rec);
   if (c.pay) (void)hipFree(c.pay);
   if (c.top) (void)hipFree(c.top);
+  if (c.mark) (void)hipFree(c.mark);
   c = DevCanvas();
 }
 
@@ -474,6 +477,22 @@ int cvx_pool_nodes(cvx_ctx* ctx, int canvas_id, uint64_t* n_nodes) {
   return CVX_OK;
 }
 
+int cvx_read_records(cvx_ctx* ctx, int canvas_id, uint64_t first, uint64_t count, uint32_t* out) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  const DevCanvas& c = ctx->canvases[canvas_id];
+  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  if (first > c.n_nodes || count > c.n_nodes - first || (count && !out))
+    return fail(ctx, CVX_ERR_INVALID_ARG, "record range outside the pool");
+  if (!count) return CVX_OK;
+  CVX_HIP(hipSetDevice(ctx->device));
+  CVX_HIP(hipStreamSynchronize(ctx->stream));
+  CVX_HIP(hipMemcpy(out, (const uint8_t*)c.rec + first * 16, count * 16, hipMemcpyDeviceToHost));
+  return CVX_OK;
+}
+
 namespace {
 
 // The checks cvx_upload_pool makes on a leaf record.
@@ -551,6 +570,7 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
   uint64_t n_cur = c.n_nodes;
   std::vector<uint32_t> touched;                   // nodes whose record word changes
   std::vector<std::pair<uint32_t, uint64_t>> paint;  // (node, payload index), in order
+  std::unordered_map<uint32_t, uint32_t> changed;   // refined or coarsened node -> depth
   auto set_x = [&](uint32_t i, uint32_t x) {
     undo.emplace_back(i, c.mirror[i]);
     c.mirror[i] = x;
@@ -566,27 +586,27 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
   };
   for (uint32_t e = 0; e < n_edits; ++e) {
     const cvx_edit& ed = edits[e];
-    const std::string at = "edit " + std::to_string(e) + ": ";
+    auto at = [e](const char* m) { return "edit " + std::to_string(e) + ": " + m; };
     if (first_child_out) first_child_out[e] = CVX_NONE_ID;
-    if (ed.node >= n_cur) return rollback(CVX_ERR_INVALID_ARG, at + "node out of range");
+    if (ed.node >= n_cur) return rollback(CVX_ERR_INVALID_ARG, at("node out of range"));
     const uint32_t x = c.mirror[ed.node];
-    if (x == CVX_FREE) return rollback(CVX_ERR_INVALID_ARG, at + "node is not in the tree");
+    if (x == CVX_FREE) return rollback(CVX_ERR_INVALID_ARG, at("node is not in the tree"));
     const bool leaf = (x & 1u) != 0;
     const uint32_t np = ed.op == CVX_EDIT_REFINE ? 8u : 1u;
-    if (ed.op > CVX_EDIT_COARSEN) return rollback(CVX_ERR_INVALID_ARG, at + "unknown op");
+    if (ed.op > CVX_EDIT_COARSEN) return rollback(CVX_ERR_INVALID_ARG, at("unknown op"));
     if (ed.first_payload > n_payloads || n_payloads - ed.first_payload < np)
-      return rollback(CVX_ERR_INVALID_ARG, at + "payload index out of range");
+      return rollback(CVX_ERR_INVALID_ARG, at("payload index out of range"));
     for (uint32_t j = 0; j < np; ++j)
       if (!leaf_ok(payloads, ed.first_payload + j, fmt))
-        return rollback(CVX_ERR_INVALID_ARG, at + "payload not finite or kappa < 0");
+        return rollback(CVX_ERR_INVALID_ARG, at("payload not finite or kappa < 0"));
     if (ed.op == CVX_EDIT_PAINT) {
-      if (!leaf) return rollback(CVX_ERR_INVALID_ARG, at + "PAINT needs a leaf");
+      if (!leaf) return rollback(CVX_ERR_INVALID_ARG, at("PAINT needs a leaf"));
       paint.emplace_back(ed.node, ed.first_payload);
     } else if (ed.op == CVX_EDIT_REFINE) {
-      if (!leaf) return rollback(CVX_ERR_INVALID_ARG, at + "REFINE needs a leaf");
+      if (!leaf) return rollback(CVX_ERR_INVALID_ARG, at("REFINE needs a leaf"));
       const uint32_t d = (x >> 1) & 63u;
       if (d + 1 > c.desc.max_depth)
-        return rollback(CVX_ERR_INVALID_ARG, at + "REFINE beyond the canvas max_depth");
+        return rollback(CVX_ERR_INVALID_ARG, at("REFINE beyond the canvas max_depth"));
       uint64_t g;
       if (!c.free_groups.empty()) {
         g = c.free_groups.back();
@@ -594,7 +614,7 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
       } else {
         g = (n_cur + 7) & ~7ull;
         if (g + 8 > (uint64_t)CVX_LEAF_BIT)
-          return rollback(CVX_ERR_INVALID_ARG, at + "pool would exceed 2^31 nodes");
+          return rollback(CVX_ERR_INVALID_ARG, at("pool would exceed 2^31 nodes"));
         c.mirror.resize(g + 8, CVX_FREE);
         n_cur = g + 8;
       }
@@ -602,23 +622,29 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
       for (uint32_t o = 0; o < 8; ++o) {
         set_x((uint32_t)g + o, 1u | ((d + 1) << 1));
         paint.emplace_back((uint32_t)g + o, ed.first_payload + o);
+        changed.erase((uint32_t)g + o);  // new children: covered by their parent
       }
+      changed[ed.node] = d;
       --c.leaves_at_depth[d];
       c.leaves_at_depth[d + 1] += 8;
       ++c.n_refined;
       if (first_child_out) first_child_out[e] = (uint32_t)g;
     } else {
-      if (leaf) return rollback(CVX_ERR_INVALID_ARG, at + "COARSEN needs a refined node");
+      if (leaf) return rollback(CVX_ERR_INVALID_ARG, at("COARSEN needs a refined node"));
       const uint32_t g = x;
       uint32_t dc = 0;
       for (uint32_t o = 0; o < 8; ++o) {
         const uint32_t cx = c.mirror[g + o];
         if (cx == CVX_FREE || !(cx & 1u))
-          return rollback(CVX_ERR_INVALID_ARG, at + "COARSEN needs 8 leaf children");
+          return rollback(CVX_ERR_INVALID_ARG, at("COARSEN needs 8 leaf children"));
         dc = (cx >> 1) & 63u;
       }
       set_x(ed.node, 1u | ((dc - 1) << 1));
-      for (uint32_t o = 0; o < 8; ++o) set_x(g + o, CVX_FREE);
+      for (uint32_t o = 0; o < 8; ++o) {
+        set_x(g + o, CVX_FREE);
+        changed.erase(g + o);            // no longer in the tree
+      }
+      changed[ed.node] = dc - 1;
       c.free_groups.push_back(g);
       c.leaves_at_depth[dc] -= 8;
       ++c.leaves_at_depth[dc - 1];
@@ -694,16 +720,17 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
     pay_ids[j] = last[j].first;
     std::memcpy(pay_src.data() + j * lb, (const uint8_t*)payloads + last[j].second * lb, lb);
   }
-  const uint64_t n_internal = c.n_refined;
-  std::vector<uint32_t> roots;
-  const uint32_t R = c.desc.R, R3 = R * R * R;
-  for (uint32_t i = 0; i < R3; ++i)
-    if (!(c.mirror[i] & 1u)) roots.push_back(i);
+  const uint32_t R = c.desc.R;
   uint32_t depth = 0;
   for (uint32_t d = 0; d < 64; ++d)
     if (c.leaves_at_depth[d]) depth = d;
+  std::vector<uint32_t> ch_ids, ch_depth;
+  for (const auto& kv : changed) {
+    ch_ids.push_back(kv.first);
+    ch_depth.push_back(kv.second);
+  }
 
-  DevBuf b_ids, b_xs, b_pids, b_psrc, b_order, b_count;
+  DevBuf b_ids, b_xs, b_pids, b_psrc, b_order, b_count, b_ch, b_chd, b_roots, b_rootd;
   hipError_t e = hipSuccess;
   const char* where = "";
 #define STEP(call)                      \
@@ -711,12 +738,25 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
     e = (call);                         \
     if (e != hipSuccess) where = #call; \
   }
+  const uint64_t n_changed = ch_ids.size();
   STEP(hipMalloc(&b_ids.p, std::max<size_t>(touched.size(), 1) * 4));
   STEP(hipMalloc(&b_xs.p, std::max<size_t>(touched.size(), 1) * 4));
   STEP(hipMalloc(&b_pids.p, std::max<size_t>(pay_ids.size(), 1) * 4));
   STEP(hipMalloc(&b_psrc.p, std::max<size_t>(pay_src.size(), 8)));
-  STEP(hipMalloc(&b_order.p, std::max<uint64_t>(n_internal, 1) * 4));
+  STEP(hipMalloc(&b_ch.p, std::max<uint64_t>(n_changed, 1) * 4));
+  STEP(hipMalloc(&b_chd.p, std::max<uint64_t>(n_changed, 1) * 4));
+  STEP(hipMalloc(&b_roots.p, std::max<uint64_t>(7 * n_changed, 1) * 4));
+  STEP(hipMalloc(&b_rootd.p, std::max<uint64_t>(7 * n_changed, 1) * 4));
   STEP(hipMalloc(&b_count.p, 4));
+  if (e == hipSuccess && c.mark_cap < c.n_nodes) {
+    // per-node visit marks of the link rebuild (epochs), grown with the pool
+    if (c.mark) (void)hipFree(c.mark);
+    c.mark = nullptr;
+    c.mark_cap = 0;
+    STEP(hipMalloc((void**)&c.mark, c.cap_nodes * 4));
+    STEP(hipMemsetAsync(c.mark, 0, c.cap_nodes * 4, ctx->stream));
+    if (e == hipSuccess) c.mark_cap = c.cap_nodes;
+  }
   if (e != hipSuccess) return device_fail(e, where);
   if (!touched.empty()) {
     STEP(hipMemcpyAsync(b_ids.p, touched.data(), touched.size() * 4, hipMemcpyHostToDevice, ctx->stream));
@@ -736,26 +776,72 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
       if (le != hipSuccess) { e = (hipError_t)le; where = "k_scatter_payloads"; }
     }
   }
-  // G_3, level by level from the refined roots (their links are the root
-  // array's and never change)
-  if (!roots.empty())
-    STEP(hipMemcpyAsync(b_order.p, roots.data(), roots.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-  uint64_t lo = 0, hi = roots.size();
-  for (uint32_t level = 0; e == hipSuccess && hi > lo; ++level) {
-    const uint32_t h32 = (uint32_t)hi;
-    STEP(hipMemcpyAsync(b_count.p, &h32, 4, hipMemcpyHostToDevice, ctx->stream));
-    if (e != hipSuccess) break;
-    int le = cvx::launch_links_level(ctx->stream, (const uint32_t*)b_order.p + lo, hi - lo, level,
-                                     c.rec, R, (uint32_t*)b_order.p, (uint32_t*)b_count.p,
-                                     c.n_nodes);
-    if (le != hipSuccess) { e = (hipError_t)le; where = "k_links_level"; break; }
+  // G_3 below the changed regions (Sec. 4.1.2), on the final records: the
+  // roots of the regions come from the device, then the links are derived
+  // level by level as at upload, each level's frontier being the refined
+  // children reached from the level above plus the region roots of that depth
+  std::map<uint32_t, std::vector<uint32_t>> roots_at;
+  uint64_t n_roots = 0;
+  if (n_changed) {
+    const uint32_t zero = 0;
+    STEP(hipMemcpyAsync(b_ch.p, ch_ids.data(), n_changed * 4, hipMemcpyHostToDevice, ctx->stream));
+    STEP(hipMemcpyAsync(b_chd.p, ch_depth.data(), n_changed * 4, hipMemcpyHostToDevice, ctx->stream));
+    STEP(hipMemcpyAsync(b_count.p, &zero, 4, hipMemcpyHostToDevice, ctx->stream));
+    if (e == hipSuccess) {
+      int le = cvx::launch_dirty_roots(ctx->stream, (const uint32_t*)b_ch.p, (const uint32_t*)b_chd.p,
+                                       n_changed, c.rec, R, (uint32_t*)b_roots.p,
+                                       (uint32_t*)b_rootd.p, (uint32_t*)b_count.p, c.n_nodes);
+      if (le != hipSuccess) { e = (hipError_t)le; where = "k_dirty_roots"; }
+    }
     uint32_t cnt = 0;
     STEP(hipMemcpyAsync(&cnt, b_count.p, 4, hipMemcpyDeviceToHost, ctx->stream));
     STEP(hipStreamSynchronize(ctx->stream));
-    if (e != hipSuccess) break;
-    if (cnt > n_internal) { e = hipErrorUnknown; where = "G_3 rebuild frontier overflow"; break; }
-    lo = hi;
-    hi = cnt;
+    if (e == hipSuccess && cnt > 7 * n_changed) { e = hipErrorUnknown; where = "region roots overflow"; }
+    std::vector<uint32_t> rid(cnt), rd(cnt);
+    if (cnt) {
+      STEP(hipMemcpy(rid.data(), b_roots.p, cnt * 4, hipMemcpyDeviceToHost));
+      STEP(hipMemcpy(rd.data(), b_rootd.p, cnt * 4, hipMemcpyDeviceToHost));
+    }
+    for (uint32_t j = 0; e == hipSuccess && j < cnt; ++j) roots_at[rd[j]].push_back(rid[j]);
+    for (auto& kv : roots_at) {
+      std::sort(kv.second.begin(), kv.second.end());
+      kv.second.erase(std::unique(kv.second.begin(), kv.second.end()), kv.second.end());
+      n_roots += kv.second.size();
+    }
+  }
+  if (e == hipSuccess && !roots_at.empty()) {
+    const uint64_t cap = c.n_refined + n_roots;
+    STEP(hipMalloc(&b_order.p, std::max<uint64_t>(cap, 1) * 4));
+    const uint32_t epoch = ++c.epoch;  // marks hold 0 or an earlier epoch
+    uint64_t lo = 0, hi = 0;
+    auto it = roots_at.begin();
+    for (uint32_t level = it->first; e == hipSuccess; ++level) {
+      if (it != roots_at.end() && it->first == level) {
+        if (hi + it->second.size() > cap) { e = hipErrorUnknown; where = "link frontier overflow"; break; }
+        STEP(hipMemcpyAsync((uint32_t*)b_order.p + hi, it->second.data(), it->second.size() * 4,
+                            hipMemcpyHostToDevice, ctx->stream));
+        hi += it->second.size();
+        ++it;
+      }
+      if (hi == lo) {
+        if (it == roots_at.end()) break;
+        continue;
+      }
+      const uint32_t h32 = (uint32_t)hi;
+      STEP(hipMemcpyAsync(b_count.p, &h32, 4, hipMemcpyHostToDevice, ctx->stream));
+      if (e != hipSuccess) break;
+      int le = cvx::launch_links_level(ctx->stream, (const uint32_t*)b_order.p + lo, hi - lo, level,
+                                       c.rec, R, (uint32_t*)b_order.p, (uint32_t*)b_count.p,
+                                       c.n_nodes, c.mark, epoch);
+      if (le != hipSuccess) { e = (hipError_t)le; where = "k_links_level"; break; }
+      uint32_t cnt = 0;
+      STEP(hipMemcpyAsync(&cnt, b_count.p, 4, hipMemcpyDeviceToHost, ctx->stream));
+      STEP(hipStreamSynchronize(ctx->stream));
+      if (e != hipSuccess) break;
+      if (cnt > cap) { e = hipErrorUnknown; where = "link frontier overflow"; break; }
+      lo = hi;
+      hi = cnt;
+    }
   }
   // top-level table for the new depth
   const uint32_t L = cvx::top_table_depth(R, depth);

@@ -51,6 +51,9 @@ struct DevCanvas {
   std::vector<uint32_t> free_groups;
   std::vector<uint64_t> leaves_at_depth;
   uint64_t n_refined = 0;  // refined nodes in the tree
+  uint32_t* mark = nullptr;  // per node: last edit call whose link rebuild visited it
+  uint64_t mark_cap = 0;
+  uint32_t epoch = 0;
 };
 
 // Depth of the top-level table of a canvas: at most 6 levels and 2^18 cells,
@@ -130,7 +133,10 @@ int launch_scatter_payloads(void* stream, const uint32_t* ids, const void* src, 
                             uint32_t leaf_bytes, void* pay);
 int launch_links_level(void* stream, const uint32_t* frontier, uint64_t n, uint32_t level,
                        void* rec, uint32_t R, uint32_t* next, uint32_t* next_count,
-                       uint64_t n_nodes);
+                       uint64_t n_nodes, uint32_t* mark, uint32_t epoch);
+int launch_dirty_roots(void* stream, const uint32_t* changed, const uint32_t* depth, uint64_t n,
+                       const void* rec, uint32_t R, uint32_t* out, uint32_t* out_depth,
+                       uint32_t* out_count, uint64_t n_nodes);
 int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, uint64_t end,
                           uint32_t level, const void* raw_nodes, const void* raw_leaves,
                           uint32_t fmt, void* rec, void* pay, uint32_t R);

@@ -122,12 +122,17 @@ int launch_extract_x(void* stream, const void* rec, uint64_t n, uint32_t* out) {
 }
 
 // Record words x of touched nodes (first child, 1 | depth << 1, or CVX_FREE).
+// A node that stays in the tree keeps its links (they depend on its parent,
+// which did not change); a node leaving the tree gets null links.
 __global__ void k_scatter_records(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ xs,
                                   uint64_t n, uint4* __restrict__ rec) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint4 r = make_uint4(xs[i], CVX_NONE, CVX_NONE, CVX_NONE);
-  rec[ids[i]] = r;
+  const uint32_t x = xs[i];
+  if (x == CVX_FREE)
+    rec[ids[i]] = make_uint4(CVX_FREE, CVX_NONE, CVX_NONE, CVX_NONE);
+  else
+    ((uint32_t*)&rec[ids[i]])[0] = x;
 }
 
 // Payloads of touched leaves, lb bytes each (8 or 32, so whole uint2 words).
@@ -146,10 +151,14 @@ __global__ void k_scatter_payloads(const uint32_t* __restrict__ ids, const uint2
 // the links of level `level` are read.
 __global__ void k_links_level(const uint32_t* __restrict__ frontier, uint64_t n, uint32_t level,
                               uint4* rec, uint32_t R, uint32_t* __restrict__ next,
-                              uint32_t* __restrict__ next_count, uint64_t n_nodes) {
+                              uint32_t* __restrict__ next_count, uint64_t n_nodes,
+                              uint32_t* __restrict__ mark, uint32_t epoch) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t P = frontier[i];
+  // a node listed twice in one frontier (reached from its parent and named
+  // as a root of a changed region) is processed once
+  if (mark && atomicExch(&mark[P], epoch) == epoch) return;
   const uint32_t first = rec[P].x;
   if ((first & 1u) || (uint64_t)first + 8 > n_nodes) return;
   for (uint32_t o = 0; o < 8; ++o) {
@@ -169,6 +178,60 @@ __global__ void k_links_level(const uint32_t* __restrict__ frontier, uint64_t n,
     w[3] = link[2];
     if (!(rec[C].x & 1u)) next[atomicAdd(next_count, 1u)] = C;
   }
+}
+
+// Roots of the regions whose links a batch of edits can change.  A node's
+// links depend only on its parent's links and on the record words of the
+// parent's face neighbours; so after the nodes `changed` (depth `depth`)
+// were refined or coarsened, every changed link lies strictly below one of:
+// a changed node that is refined (its children are new), or a refined
+// same-depth face neighbour of a changed node (a sibling, a same-depth outer
+// link, or at depth 0 a neighbouring root).  Outer links to coarser cells
+// are leaves and have nothing below them.
+__global__ void k_dirty_roots(const uint32_t* __restrict__ changed,
+                              const uint32_t* __restrict__ depth, uint64_t n,
+                              const uint4* __restrict__ rec, uint32_t R,
+                              uint32_t* __restrict__ out, uint32_t* __restrict__ out_depth,
+                              uint32_t* __restrict__ out_count, uint64_t n_nodes) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t X = changed[i], d = depth[i];
+  uint32_t cand[7];
+  cand[0] = X;
+  if (d == 0) {
+    const uint32_t c[3] = {X % R, (X / R) % R, X / (R * R)};
+    for (uint32_t k = 0; k < 3; ++k) {
+      const uint32_t stride = k == 0 ? 1u : (k == 1 ? R : R * R);
+      cand[1 + 2 * k] = c[k] + 1 < R ? X + stride : CVX_NONE;
+      cand[2 + 2 * k] = c[k] > 0 ? X - stride : CVX_NONE;
+    }
+  } else {
+    const uint4 r = rec[X];
+    for (uint32_t k = 0; k < 3; ++k) cand[1 + k] = X ^ (1u << k);
+    cand[4] = r.y;
+    cand[5] = r.z;
+    cand[6] = r.w;
+  }
+  for (uint32_t j = 0; j < 7; ++j) {
+    const uint32_t N = cand[j];
+    if (N == CVX_NONE || (uint64_t)N >= n_nodes) continue;
+    const uint32_t x = rec[N].x;
+    if (x == CVX_FREE || (x & 1u)) continue;
+    const uint32_t slot = atomicAdd(out_count, 1u);
+    out[slot] = N;
+    out_depth[slot] = d;
+  }
+}
+
+int launch_dirty_roots(void* stream, const uint32_t* changed, const uint32_t* depth, uint64_t n,
+                       const void* rec, uint32_t R, uint32_t* out, uint32_t* out_depth,
+                       uint32_t* out_count, uint64_t n_nodes) {
+  if (!n) return hipSuccess;
+  const uint32_t bs = 256;
+  hipLaunchKernelGGL(k_dirty_roots, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, changed, depth, n, (const uint4*)rec, R, out, out_depth,
+                     out_count, n_nodes);
+  return (int)hipGetLastError();
 }
 
 int launch_scatter_records(void* stream, const uint32_t* ids, const uint32_t* xs, uint64_t n,
@@ -191,12 +254,12 @@ int launch_scatter_payloads(void* stream, const uint32_t* ids, const void* src, 
 
 int launch_links_level(void* stream, const uint32_t* frontier, uint64_t n, uint32_t level,
                        void* rec, uint32_t R, uint32_t* next, uint32_t* next_count,
-                       uint64_t n_nodes) {
+                       uint64_t n_nodes, uint32_t* mark, uint32_t epoch) {
   if (!n) return hipSuccess;
   const uint32_t bs = 256;
   hipLaunchKernelGGL(k_links_level, dim3((uint32_t)((n + bs - 1) / bs)), dim3(bs), 0,
                      (hipStream_t)stream, frontier, n, level, (uint4*)rec, R, next, next_count,
-                     n_nodes);
+                     n_nodes, mark, epoch);
   return (int)hipGetLastError();
 }
 

@@ -44,7 +44,8 @@ CVX_STAT_COUNT = 8
 
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",
             "cvx_last_error", "cvx_status_str", "cvx_validate_pool", "cvx_validate_views",
-            "cvx_pool_bytes", "cvx_autotune", "cvx_edit_pool", "cvx_pool_nodes"]
+            "cvx_pool_bytes", "cvx_autotune", "cvx_edit_pool", "cvx_pool_nodes",
+            "cvx_read_records"]
 
 CVX_EDIT_PAINT = 0
 CVX_EDIT_REFINE = 1
@@ -89,6 +90,11 @@ class cvx_edit(ctypes.Structure):
                 ("first_payload", ctypes.c_uint64)]
 
 
+# the same layout as a numpy record, for building long edit lists quickly
+EDIT_DTYPE = np.dtype([("op", "<u4"), ("node", "<u4"), ("first_payload", "<u8")])
+assert EDIT_DTYPE.itemsize == ctypes.sizeof(cvx_edit)
+
+
 class cvx_tune_result(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_uint32), ("tile_h", ctypes.c_uint32),
                 ("wg_size", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
@@ -124,6 +130,7 @@ _lib.cvx_validate_views.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes
 _lib.cvx_pool_bytes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
 _lib.cvx_edit_pool.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, ctypes.c_uint64, _vp]
 _lib.cvx_pool_nodes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+_lib.cvx_read_records.argtypes = [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, _vp]
 _lib.cvx_autotune.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(cvx_render_opts),
                               ctypes.c_uint32, ctypes.POINTER(cvx_render_opts),
                               ctypes.POINTER(cvx_tune_result), ctypes.c_uint32,
@@ -210,16 +217,20 @@ def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
 
 
 def cvx_edit_pool(ctx, canvas_id, edits, payloads):
-    """edits: sequence of (op, node, first_payload); payloads: leaf records in the
-    pool's format (numpy structured array).  Returns the first child id per edit
-    (CVX_NONE_ID for edits that are not REFINE)."""
+    """edits: sequence of (op, node, first_payload) or an EDIT_DTYPE array;
+    payloads: leaf records in the pool's format (numpy structured array).
+    Returns the first child id per edit (CVX_NONE_ID for edits that are not
+    REFINE)."""
     n = len(edits)
-    arr = (cvx_edit * max(n, 1))()
-    for i, (op, node, fp) in enumerate(edits):
-        arr[i].op, arr[i].node, arr[i].first_payload = int(op), int(node), int(fp)
+    if isinstance(edits, np.ndarray) and edits.dtype == EDIT_DTYPE:
+        arr = np.ascontiguousarray(edits)
+    elif n:
+        arr = np.array([(int(a), int(b), int(c)) for a, b, c in edits], EDIT_DTYPE)
+    else:
+        arr = np.zeros(1, EDIT_DTYPE)
     payloads = np.ascontiguousarray(payloads)
     out = np.full(max(n, 1), CVX_NONE_ID, np.uint32)
-    _check(ctx, _lib.cvx_edit_pool(ctx, int(canvas_id), ctypes.cast(arr, _vp), n,
+    _check(ctx, _lib.cvx_edit_pool(ctx, int(canvas_id), arr.ctypes.data, n,
                                    payloads.ctypes.data if len(payloads) else None, len(payloads),
                                    out.ctypes.data))
     return out[:n]
@@ -229,6 +240,16 @@ def cvx_pool_nodes(ctx, canvas_id) -> int:
     b = ctypes.c_uint64()
     _check(ctx, _lib.cvx_pool_nodes(ctx, int(canvas_id), ctypes.byref(b)))
     return int(b.value)
+
+
+def cvx_read_records(ctx, canvas_id, first=0, count=None):
+    """Device node records as an (count, 4) uint32 array (diagnostic)."""
+    if count is None:
+        count = cvx_pool_nodes(ctx, canvas_id) - first
+    out = np.zeros((count, 4), np.uint32)
+    _check(ctx, _lib.cvx_read_records(ctx, int(canvas_id), int(first), int(count),
+                                      out.ctypes.data if count else None))
+    return out
 
 
 def cvx_free_pool(ctx, canvas_id):

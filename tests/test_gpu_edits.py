@@ -48,6 +48,9 @@ def _check_against_model(sess, m, views, variant, tol):
     exp = m.canvas()
     assert cvx.cvx_pool_nodes(sess.ctx, 0) == exp.n_nodes
     sess.upload(1, exp)
+    # every record word and every outer-face link equals a fresh upload's
+    np.testing.assert_array_equal(cvx.cvx_read_records(sess.ctx, 0),
+                                  cvx.cvx_read_records(sess.ctx, 1))
     a = sess.render(views, variant).cpu().numpy()
     b = sess.render([dict(v, canvas_id=1) for v in views], variant).cpu().numpy()
     np.testing.assert_array_equal(a, b)
@@ -111,6 +114,30 @@ def test_pool_grows_and_reuses_freed_groups(sess):
     _check_against_model(sess, m, views, "fp32_rebased", 1e-3)
 
 
+def test_edits_next_to_deep_subtrees(sess):
+    """Refine, then coarsen again, every shallow leaf of a tree refined along
+    one path to depth 14: the deep cells next to them link to them as their
+    coarser neighbours, so their links must follow both changes."""
+    from paper_1704_02724_amd import cvx
+    cv = trees.deep_path_tree(14, seed=87, leaf_format=LEAF_RGBA8_F16, halo=1)
+    m = PoolModel(cv)
+    sess.upload(0, cv)
+    rng = np.random.Generator(np.random.PCG64(87))
+    views = _views(rng, 2, 32, 32)
+    shallow = sorted(i for i in m.leaves_list() if m.state[i] <= 4)
+    assert len(shallow) > 20
+    edits = [(REFINE, n, 8 * i) for i, n in enumerate(shallow)]
+    pays = [payload_rgba8(rng) for _ in range(8 * len(shallow))]
+    np.testing.assert_array_equal(sess.edit(0, edits, _pays(pays, LEAF_RGBA8_F16)),
+                                  m.apply(edits, pays))
+    _check_against_model(sess, m, views, "fp32_rebased", 1e-3)
+    edits = [(COARSEN, n, i) for i, n in enumerate(shallow)]
+    pays = [payload_rgba8(rng) for _ in shallow]
+    m.apply(edits, pays)
+    sess.edit(0, edits, _pays(pays, LEAF_RGBA8_F16))
+    _check_against_model(sess, m, views, "fp32_rebased", 1e-3)
+
+
 def test_rejected_edits_change_nothing(sess):
     from paper_1704_02724_amd import cvx
     cv = trees.random_tree(1, 4, seed=86, max_nodes=3000, leaf_format=LEAF_RGBA8_F16)
@@ -120,6 +147,7 @@ def test_rejected_edits_change_nothing(sess):
     views = _views(rng, 1, 32, 24)
     ref = sess.render(views).cpu().numpy()
     n0 = cvx.cvx_pool_nodes(sess.ctx, 0)
+    rec0 = cvx.cvx_read_records(sess.ctx, 0)
     leaves = [i for i in m.leaves_list() if m.state[i] < m.max_depth]
     deepest = [i for i in m.leaves_list() if m.state[i] == m.max_depth]
     internal = [i for i in m.state if m.is_refined(i)]
@@ -149,6 +177,7 @@ def test_rejected_edits_change_nothing(sess):
         assert e.value.code == cvx.CVX_ERR_INVALID_ARG, edits
         np.testing.assert_array_equal(sess.render(views).cpu().numpy(), ref)
         assert cvx.cvx_pool_nodes(sess.ctx, 0) == n0
+        np.testing.assert_array_equal(cvx.cvx_read_records(sess.ctx, 0), rec0)
     # a freed node is no longer in the tree
     node = leaves[3]
     g = sess.edit(0, [(REFINE, node, 0)], P)[0]
