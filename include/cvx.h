@@ -59,6 +59,8 @@ extern "C" {
 #define CVX_VARIANT_FP32_NAIVE 2u   /* FP32 canvas-global traversal (drifts at depth) */
 #define CVX_VARIANT_FP32_CELL_LOCAL 3u /* the paper's uncertified FP32 cell-local traversal
                                           (Sec. 6.2), for the precision experiment */
+#define CVX_VARIANT_FP16_CELL_LOCAL 4u /* the same traversal in IEEE half precision (the
+                                          closing remark of Sec. 6.3), for the experiment */
 
 #define CVX_MAX_CANVASES 64
 #define CVX_MAX_DEPTH 30

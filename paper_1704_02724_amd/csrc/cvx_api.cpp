@@ -301,7 +301,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   ctx->err.clear();
   cvx_render_opts o{};
   if (opts) o = *opts;
-  if (o.variant > CVX_VARIANT_FP32_CELL_LOCAL)
+  if (o.variant > CVX_VARIANT_FP16_CELL_LOCAL)
     return fail(ctx, CVX_ERR_INVALID_ARG, "unknown variant");
   uint32_t tw = o.tile_w ? o.tile_w : 8, th = o.tile_h ? o.tile_h : 8;
   if (tw * th != 64 || tw == 0 || th == 0)

@@ -23,6 +23,8 @@
 //                traversal that drifts at depth); kept to show the failure.
 //  FP32_CELL_LOCAL  the paper's own cell-local FP32 traversal (Sec. 6.2),
 //                uncertified; the subject of its error analysis (Sec. 6.3).
+//  FP16_CELL_LOCAL  the same traversal in IEEE half precision, the case the
+//                end of Sec. 6.3 argues would suffice.
 #include <hip/hip_runtime.h>
 
 #include "cvx_internal.h"
@@ -789,26 +791,37 @@ __device__ void cast_naive(const DView& v, const V3<double>& d, const Entry& en,
 }
 
 // ----------------------------------------------------------------------------
-// FP32_CELL_LOCAL: the paper's traversal (Sec. 6.2).  The entry point p of the
-// current leaf is held in the leaf's own frame (origin at its centre, edge 1)
-// in FP32; the exit face is the argmin of t_k = (+-0.5 - p_k) / d_k, the exit
-// point p' = p + t d, and p' is mapped into the next cell by a power-of-two
-// scale and a shift (across a face: shift by one edge on that axis; into a
-// coarser leaf: scale by 2^-m after the integer offset of the finer cell; into
-// a refined cell: child by the sign of p, then p -> 2p - b + 1/2 per level).
-// The start point is the only FP64 step (rounded once into the first leaf's
-// frame).  Nothing is certified: this is the scheme whose error Sec. 6.3
-// bounds, measured by the precision experiment.
+// FP32_CELL_LOCAL / FP16_CELL_LOCAL: the paper's traversal (Sec. 6.2).  The
+// entry point p of the current leaf is held in the leaf's own frame (origin at
+// its centre, edge 1) in FP32 (or FP16); the exit face is the argmin of
+// t_k = (+-0.5 - p_k) / d_k, the exit point p' = p + t d, and p' is mapped into
+// the next cell by a power-of-two scale and a shift (across a face: shift by
+// one edge on that axis; into a coarser leaf: scale by 2^-m after the integer
+// offset of the finer cell; into a refined cell: child by the sign of p, then
+// p -> 2p - b + 1/2 per level).  The start point is the only FP64 step
+// (rounded once into the first leaf's frame).  Nothing is certified: this is
+// the scheme whose error Sec. 6.3 bounds, measured by the precision
+// experiment.  In FP16 every operation of the traversal (t, p', the frame
+// changes, the ray direction itself) is rounded to half precision; a coarser
+// leaf's frame change is p' s + c with s = 2^-m and c = (offset + 1/2) s - 1/2
+// each rounded once to half.  Compositing stays in FP32 in both.
 // ----------------------------------------------------------------------------
-template <bool TRACE, bool STATS>
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ _Float16 fma_r(_Float16 a, _Float16 b, _Float16 c) {
+  return __builtin_fmaf16(a, b, c);
+}
+
+template <class Real, bool TRACE, bool STATS>
 __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
                            Sink sk, Acc& acc, Out& out) {
+  constexpr bool HALF = __is_same(Real, _Float16);
+  const Real inf = (Real)__builtin_inff();
   const V3<double> o{v.o[0], v.o[1], v.o[2]};
   const double Rd = (double)v.R;
   const void* rec = v.rec;
   const void* payp = v.pay;
   const bool use_stop = v.alpha_stop < 1.0f;
-  const V3<float> df{(float)d.x, (float)d.y, (float)d.z};
+  const V3<Real> df{(Real)d.x, (Real)d.y, (Real)d.z};
   V3<double> q;
   for (int k = 0; k < 3; ++k) {
     double qk = get(o, k) + en.t0 * get(d, k);
@@ -822,9 +835,9 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
   locate_top(v, C0, I, dep, c, r);
   bool bad = !descend_int(rec, v.n_nodes, C0, v.max_depth, I, dep, c, r);
   if (STATS) acc.descent += dep;
-  V3<float> p;
+  V3<Real> p;
   for (int k = 0; k < 3; ++k)
-    set(p, k, (float)(ldexp(get(q, k), (int)dep) - (double)get(c, k) - 0.5));
+    set(p, k, (Real)(ldexp(get(q, k), (int)dep) - (double)get(c, k) - 0.5));
   float T = 1.0f;
   V3<float> C{0.f, 0.f, 0.f};
   uint32_t n_rec = 0;
@@ -832,30 +845,32 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
   for (;; ++step) {
     if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
     if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
-    float best = BIGF;
+    Real best = HALF ? inf : (Real)BIGF;
     int kx = 0;
     for (int k = 0; k < 3; ++k) {
-      const float face = get(up, k) ? 0.5f : -0.5f;
-      const float tt = get(df, k) == 0.0f ? BIGF : (face - get(p, k)) / get(df, k);
+      const Real face = get(up, k) ? (Real)0.5f : (Real)-0.5f;
+      const Real tt = get(df, k) == (Real)0.0f ? (HALF ? inf : (Real)BIGF)
+                                                : (face - get(p, k)) / get(df, k);
       kx = tt < best ? k : kx;
       best = tt < best ? tt : best;
     }
-    const float len = best > 0.0f ? best : 0.0f;   // leaf edges
-    V3<float> pe;
-    for (int k = 0; k < 3; ++k) set(pe, k, __builtin_fmaf(len, get(df, k), get(p, k)));
+    const Real len = best > (Real)0.0f ? best : (Real)0.0f;   // leaf edges
+    V3<Real> pe;
+    for (int k = 0; k < 3; ++k) set(pe, k, fma_r(len, get(df, k), get(p, k)));
     if (TRACE) {
       const double h = ldexp(1.0, -(int)dep);
       for (int k = 0; k < 3; ++k)
         out.end[k] = ((double)get(c, k) + 0.5 + (double)get(pe, k)) * h;
     }
     const uint2 pay = ld_pay(payp, I);
-    const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * len * -1.4426950408889634f);
+    const float lenf = (float)len;
+    const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * lenf * -1.4426950408889634f);
     const float a = T - Tn;
     C.x = __builtin_fmaf(a, (float)(pay.x & 0xffu), C.x);
     C.y = __builtin_fmaf(a, (float)((pay.x >> 8) & 0xffu), C.y);
     C.z = __builtin_fmaf(a, (float)((pay.x >> 16) & 0xffu), C.z);
     T = Tn;
-    if (TRACE) record(sk, n_rec, I, len);
+    if (TRACE) record(sk, n_rec, I, lenf);
     ++n_rec;
     const uint32_t ck = get(c, kx);
     const bool upk = get(up, kx);
@@ -867,7 +882,7 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
     if (STATS) acc.outer += mv.outer;
     // across the face: one edge along kx
     p = pe;
-    set(p, kx, get(pe, kx) - (upk ? 1.0f : -1.0f));
+    set(p, kx, get(pe, kx) - (upk ? (Real)1.0f : (Real)-1.0f));
     set(c, kx, mv.nc);
     I = mv.N;
     r = ld_rec(rec, I);
@@ -879,7 +894,10 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
       const uint32_t mask = (1u << m) - 1u;
       for (int k = 0; k < 3; ++k) {
         const float off = (float)(get(c, k) & mask);
-        set(p, k, __builtin_fmaf(get(p, k) + 0.5f + off, sc, -0.5f));
+        if constexpr (HALF)
+          set(p, k, fma_r(get(p, k), (Real)sc, (Real)__builtin_fmaf(off + 0.5f, sc, -0.5f)));
+        else
+          set(p, k, __builtin_fmaf(get(p, k) + 0.5f + off, sc, -0.5f));
         set(c, k, get(c, k) >> m);
       }
       dep -= m;
@@ -890,10 +908,10 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
         if (r.x >= v.n_nodes - 7u) { bad = true; break; }
         uint32_t oct = 0;
         for (int k = 0; k < 3; ++k) {
-          const float pk = get(p, k);
-          const uint32_t b = (pk > 0.0f || (pk == 0.0f && get(up, k))) ? 1u : 0u;
+          const Real pk = get(p, k);
+          const uint32_t b = (pk > (Real)0.0f || (pk == (Real)0.0f && get(up, k))) ? 1u : 0u;
           oct |= b << k;
-          set(p, k, 2.0f * pk - (float)b + 0.5f);
+          set(p, k, (Real)2.0f * pk - (Real)(float)b + (Real)0.5f);
           set(c, k, 2u * get(c, k) + b);
         }
         I = r.x + oct;
@@ -933,8 +951,10 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
     cast_fp64<TRACE, STATS>(v, d, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP32_NAIVE) {
     cast_naive<TRACE, STATS>(v, d, en, up, sk, acc, out);
+  } else if constexpr (VAR == (int)CVX_VARIANT_FP32_CELL_LOCAL) {
+    cast_local<float, TRACE, STATS>(v, d, en, up, sk, acc, out);
   } else {
-    cast_local<TRACE, STATS>(v, d, en, up, sk, acc, out);
+    cast_local<_Float16, TRACE, STATS>(v, d, en, up, sk, acc, out);
   }
 }
 
@@ -1113,6 +1133,9 @@ int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out
                                                    wg_size);
     case CVX_VARIANT_FP32_CELL_LOCAL:
       return launch_v<(int)CVX_VARIANT_FP32_CELL_LOCAL>(stream, trace, stats, false, a,
+                                                        workgroups, wg_size);
+    case CVX_VARIANT_FP16_CELL_LOCAL:
+      return launch_v<(int)CVX_VARIANT_FP16_CELL_LOCAL>(stream, trace, stats, false, a,
                                                         workgroups, wg_size);
     default:
       return (int)hipErrorInvalidValue;

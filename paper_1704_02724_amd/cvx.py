@@ -33,7 +33,9 @@ CVX_VARIANT_FP32_REBASED = 0
 CVX_VARIANT_FP64_PLAIN = 1
 CVX_VARIANT_FP32_NAIVE = 2
 CVX_VARIANT_FP32_CELL_LOCAL = 3
-VARIANTS = {"fp32_rebased": 0, "fp64_plain": 1, "fp32_naive": 2, "fp32_cell_local": 3}
+CVX_VARIANT_FP16_CELL_LOCAL = 4
+VARIANTS = {"fp32_rebased": 0, "fp64_plain": 1, "fp32_naive": 2, "fp32_cell_local": 3,
+            "fp16_cell_local": 4}
 
 CVX_RAYFLAG_STEP_CAP = 1
 CVX_RAYFLAG_FP64_EXIT = 2

@@ -8,7 +8,8 @@ d = normalize(fwd + u right + v up)); the angle error is the angle between
 (end point - eye) and d, the along-ray error the difference between the end
 point's distance along d and the exact canvas exit, over the chord length L.
 The paper's stated worst case for its cell-local scheme is an angle of
-asin(sqrt(2) (e0 / L + 7.5 eps)) with eps = 2^-23 (e0 = start-point error).
+asin(sqrt(2) (e0 / L + 7.5 eps)) with eps = 2^-23 (e0 = start-point error);
+for the half-precision traversal eps = 2^-10.
 
     python -m paper_1704_02724_amd.precision --workload depth24
 prints one JSON summary (binned by L and by cells crossed).
@@ -23,6 +24,12 @@ import sys
 import numpy as np
 
 EPS32 = 2.0 ** -23
+EPS16 = 2.0 ** -10
+
+
+def paper_bound_deg(eps):
+    """The worst-case ray angle of Sec. 6.3 with no start-point error."""
+    return math.degrees(math.asin(math.sqrt(2) * 7.5 * eps))
 
 
 def pixel_rays(view, ids):
@@ -102,13 +109,14 @@ def summarise(m):
                 along_rel=dict(median=float(np.median(m["along_rel"])),
                                max=float(m["along_rel"].max())),
                 by_length=_bins(L, a, Le), by_cells=_bins(m["cells"], a, ce),
-                paper_bound_deg_at_e0_0=math.degrees(math.asin(math.sqrt(2) * 7.5 * EPS32)))
+                paper_bound_deg_at_e0_0=dict(fp32=paper_bound_deg(EPS32),
+                                             fp16=paper_bound_deg(EPS16)))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="depth24")
-    ap.add_argument("--variants", default="fp32_cell_local,fp32_naive,fp32_rebased,fp64_plain")
+    ap.add_argument("--variants", default="fp16_cell_local,fp32_cell_local,fp32_naive,fp32_rebased,fp64_plain")
     ap.add_argument("--max-rays", type=int, default=0)
     args = ap.parse_args()
     from canvasgen import configs
