@@ -244,10 +244,12 @@ typedef struct {
  * existing nodes never change).  If first_child_out is not NULL, it receives
  * per edit the first child id of a REFINE and CVX_NONE_ID otherwise.  Every
  * edit is checked first (node state, depth limit, payload index and kappa);
- * on any error nothing changes.  The records, payloads, the three
- * outer-face links of every node (rebuilt on the GPU level by level, as at
- * upload) and the top-level table are updated before the call returns.
- * Synchronous. */
+ * on any error nothing changes.  The records, payloads, the outer-face
+ * links (rebuilt on the GPU below the cells the edits refined or coarsened
+ * and their same-depth face neighbours) and the top-level table are updated
+ * before the call returns.  A brush stroke still in progress on the canvas
+ * (cvx_stroke_begin) is ended first: its remaining splits are dropped and the
+ * leaves keep their immediate paint.  Synchronous. */
 #define CVX_NONE_ID 0xffffffffu
 int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n_edits,
                   const void* payloads, uint64_t n_payloads, uint32_t* first_child_out);
@@ -261,6 +263,55 @@ int cvx_pool_nodes(cvx_ctx* ctx, int canvas_id, uint64_t* n_nodes);
  * neighbours on the x, y, z axes (0xffffffff for none).  Synchronous;
  * CVX_ERR_INVALID_ARG if the range passes the pool's node count. */
 int cvx_read_records(cvx_ctx* ctx, int canvas_id, uint64_t first, uint64_t count, uint32_t* out);
+
+/* Diagnostic copy of device leaf payloads [first, first + count) (indexed by
+ * node id, in the pool's leaf format; unspecified for ids that are not
+ * leaves) into the host array out.  Synchronous; CVX_ERR_INVALID_ARG if the
+ * range passes the pool's node count. */
+int cvx_read_payloads(cvx_ctx* ctx, int canvas_id, uint64_t first, uint64_t count, void* out);
+
+/* Brush strokes (Sec. 5.1-5.3).  A stroke is a list of spherical stamps
+ * (x, y, z, r in world units, as the canvas descriptor) with one brush colour,
+ * one opacity density per brush radius and one brush radius.  Its effect on
+ * a leaf: a leaf the stamps overlap (its closed box lies at a distance < r
+ * from a stamp centre) is split into 8 children while its edge exceeds
+ * radius / k_refine and it is above desc.max_depth (Sec. 5.2; children keep
+ * the colour and take half the optical depth per edge); a leaf that is not
+ * split and whose centre lies in a stamp (distance <= r) takes the stroke
+ * once: kb = sigma * edge / radius, m = kb / (kb + kappa) (0 if both are 0),
+ * colour = m * rgb + (1 - m) * colour, kappa = kb + kappa (Sec. 5.1, density
+ * as the alpha term).  RGBA8_F16 leaves are decoded (byte / 255, half kappa),
+ * mixed in FP64 and encoded again (bytes and A = 255 (1 - exp(-kappa)) rounded
+ * to nearest even, kappa to half through float).  As in Sec. 5.3 the splits
+ * are deferred: cvx_stroke_begin paints the stroke into the leaves that exist
+ * and records the leaves that still need a split; each cvx_stroke_step splits
+ * them by one level and paints the new children.  When *pending reaches 0 the
+ * canvas is the one the stroke would give applied at once. */
+typedef struct {
+  double rgb[3];   /* brush colour, each in [0, 1] */
+  double sigma;    /* opacity density per brush radius, finite, >= 0 */
+  double radius;   /* brush radius in world units, finite, > 0 */
+  double k_refine; /* leaves are split while their edge exceeds radius / k_refine; > 0 */
+} cvx_stroke;
+
+#define CVX_MAX_STAMPS 65536u
+
+/* Start a stroke on the pool under canvas_id: stamps is a host array of
+ * n_stamps (1..CVX_MAX_STAMPS) x 4 doubles, each r finite and >= 0, read
+ * during the call.  A stroke still in progress on the canvas is completed
+ * first.  *pending receives the number of leaves waiting for a split.
+ * Synchronous; on an argument error nothing changes. */
+int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, const double* stamps,
+                     uint32_t n_stamps, uint64_t* pending);
+
+/* One deferred level of the stroke in progress: every waiting leaf is split
+ * (through the same machinery as cvx_edit_pool, with children that take the
+ * leaf's payload from before the stroke), the stroke is painted into the
+ * children, and *pending receives the number of children that still need a
+ * split.  With no stroke in progress it returns CVX_OK and *pending = 0.
+ * Synchronous; on an error (e.g. CVX_ERR_OOM while the pool grows) the pool is
+ * left as after the previous step and the stroke is dropped. */
+int cvx_stroke_step(cvx_ctx* ctx, int canvas_id, uint64_t* pending);
 
 /* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
 int cvx_free_pool(cvx_ctx* ctx, int canvas_id);

@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libcvx.so")
-SOURCES = ["cvx_api.cpp", "cvx_validate.cpp", "cvx_upload.hip", "cvx_cast.hip"]
+SOURCES = ["cvx_api.cpp", "cvx_validate.cpp", "cvx_upload.hip", "cvx_cast.hip",
+           "cvx_stroke.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -544,16 +544,10 @@ struct DevBuf {
   }
 };
 
-}  // namespace
-
-int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n_edits,
-                  const void* payloads, uint64_t n_payloads, uint32_t* first_child_out) {
-  if (!ctx) return CVX_ERR_INVALID_ARG;
-  ctx->err.clear();
-  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
-    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
-  DevCanvas& c = ctx->canvases[canvas_id];
-  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+// The edits of cvx_edit_pool on a present canvas (also the splits of a
+// stroke step).
+int edit_impl(cvx_ctx* ctx, DevCanvas& c, const cvx_edit* edits, uint32_t n_edits,
+              const void* payloads, uint64_t n_payloads, uint32_t* first_child_out) {
   if (n_edits && !edits) return fail(ctx, CVX_ERR_INVALID_ARG, "edits is NULL");
   if (n_payloads && !payloads) return fail(ctx, CVX_ERR_INVALID_ARG, "payloads is NULL");
   CVX_HIP(hipSetDevice(ctx->device));
@@ -864,6 +858,284 @@ int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n
   if (e != hipSuccess) return device_fail(e, where);
   c.depth = depth;
   return CVX_OK;
+}
+
+}  // namespace
+
+int cvx_edit_pool(cvx_ctx* ctx, int canvas_id, const cvx_edit* edits, uint32_t n_edits,
+                  const void* payloads, uint64_t n_payloads, uint32_t* first_child_out) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  DevCanvas& c = ctx->canvases[canvas_id];
+  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  c.stroke = cvx::StrokeState();
+  return edit_impl(ctx, c, edits, n_edits, payloads, n_payloads, first_child_out);
+}
+
+int cvx_read_payloads(cvx_ctx* ctx, int canvas_id, uint64_t first, uint64_t count, void* out) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  const DevCanvas& c = ctx->canvases[canvas_id];
+  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  if (first > c.n_nodes || count > c.n_nodes - first || (count && !out))
+    return fail(ctx, CVX_ERR_INVALID_ARG, "payload range outside the pool");
+  if (!count) return CVX_OK;
+  const uint64_t lb = leaf_bytes(c.desc.leaf_format);
+  CVX_HIP(hipSetDevice(ctx->device));
+  CVX_HIP(hipStreamSynchronize(ctx->stream));
+  CVX_HIP(hipMemcpy(out, (const uint8_t*)c.pay + first * lb, count * lb, hipMemcpyDeviceToHost));
+  return CVX_OK;
+}
+
+namespace {
+
+// IEEE half <-> float, round to nearest even (host side of the leaf format).
+float half_to_float(uint16_t h) {
+  const uint32_t sign = (uint32_t)(h & 0x8000u) << 16, ex = (h >> 10) & 0x1fu, man = h & 0x3ffu;
+  float v;
+  if (ex == 0) {
+    v = std::ldexp((float)man, -24);
+    return sign ? -v : v;
+  }
+  const uint32_t bits = ex == 31 ? (sign | 0x7f800000u | (man << 13))
+                                 : (sign | ((ex + 112u) << 23) | (man << 13));
+  std::memcpy(&v, &bits, 4);
+  return v;
+}
+
+uint16_t float_to_half(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u, ax = x & 0x7fffffffu;
+  if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));
+  if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // 65520 and up round to inf
+  if (ax < 0x38800000u) {                                     // below 2^-14: subnormal
+    float a;
+    std::memcpy(&a, &ax, 4);
+    return (uint16_t)(sign | (uint32_t)std::nearbyint(a * 16777216.0f));
+  }
+  uint32_t h = (((ax >> 23) - 112u) << 10) | ((ax & 0x7fffffu) >> 13);
+  const uint32_t rem = ax & 0x1fffu;
+  if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;
+  return (uint16_t)(sign | h);
+}
+
+// Payload of the children of a split leaf: same colour, half the optical
+// depth per edge (A recomputed from it).
+void child_payload(const uint8_t* parent, uint32_t fmt, uint8_t* child) {
+  if (fmt == CVX_LEAF_F64) {
+    double q[4];
+    std::memcpy(q, parent, 32);
+    q[3] = q[3] * 0.5;
+    std::memcpy(child, q, 32);
+    return;
+  }
+  uint16_t h;
+  std::memcpy(&h, parent + 4, 2);
+  const uint16_t hc = float_to_half(half_to_float(h) * 0.5f);
+  const double kc = (double)half_to_float(hc);
+  std::memcpy(child, parent, 8);
+  child[3] = (uint8_t)std::lrint(255.0 * (1.0 - std::exp(-kc)));
+  std::memcpy(child + 4, &hc, 2);
+  child[6] = child[7] = 0;
+}
+
+// One walk of the stroke from a frontier (nullptr: the root array) down to
+// the leaves, level by level on the GPU; the leaves still waiting for a split
+// are appended to c.stroke.pending with their payloads from before the stroke.
+int stroke_walk(cvx_ctx* ctx, DevCanvas& c, const std::vector<cvx::StrokeItem>* start) {
+  cvx::StrokeState& st = c.stroke;
+  const uint32_t lb = leaf_bytes(c.desc.leaf_format);
+  const uint32_t R = c.desc.R;
+  uint64_t n = start ? start->size() : (uint64_t)R * R * R;
+  if (!n) return CVX_OK;
+  DevBuf b_stamps, b_cur, b_count;
+  hipError_t e = hipSuccess;
+  const char* where = "";
+#define STEP(call)                      \
+  if (e == hipSuccess) {                \
+    e = (call);                         \
+    if (e != hipSuccess) where = #call; \
+  }
+  STEP(hipMalloc(&b_stamps.p, st.stamps.size() * 8));
+  STEP(hipMemcpyAsync(b_stamps.p, st.stamps.data(), st.stamps.size() * 8, hipMemcpyHostToDevice,
+                      ctx->stream));
+  STEP(hipMalloc(&b_count.p, 8));
+  if (start) {
+    STEP(hipMalloc(&b_cur.p, n * sizeof(cvx::StrokeItem)));
+    STEP(hipMemcpyAsync(b_cur.p, start->data(), n * sizeof(cvx::StrokeItem),
+                        hipMemcpyHostToDevice, ctx->stream));
+  }
+  for (uint32_t level = 0; e == hipSuccess && n; ++level) {
+    if (n > 0x1fffffffull) { e = hipErrorUnknown; where = "stroke frontier too large"; break; }
+    DevBuf b_next, b_pend, b_ppay;
+    STEP(hipMalloc(&b_next.p, 8 * n * sizeof(cvx::StrokeItem)));
+    STEP(hipMalloc(&b_pend.p, n * sizeof(cvx::StrokeItem)));
+    STEP(hipMalloc(&b_ppay.p, n * lb));
+    STEP(hipMemsetAsync(b_count.p, 0, 8, ctx->stream));
+    if (e != hipSuccess) break;
+    uint32_t* cnt = (uint32_t*)b_count.p;
+    int le = cvx::launch_stroke_visit(ctx->stream, (const cvx::StrokeItem*)b_cur.p, (uint32_t)n,
+                                      st.args, b_stamps.p, c.rec, c.pay, c.n_nodes,
+                                      (cvx::StrokeItem*)b_next.p, cnt, (uint32_t)(8 * n),
+                                      (cvx::StrokeItem*)b_pend.p, b_ppay.p, cnt + 1, (uint32_t)n);
+    if (le != hipSuccess) { e = (hipError_t)le; where = "k_stroke_visit"; break; }
+    uint32_t h[2] = {0, 0};
+    STEP(hipMemcpyAsync(h, b_count.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+    STEP(hipStreamSynchronize(ctx->stream));
+    if (e != hipSuccess) break;
+    if (h[0] > 8 * n || h[1] > n) { e = hipErrorUnknown; where = "stroke frontier overflow"; break; }
+    if (h[1]) {
+      const size_t p0 = st.pending.size();
+      st.pending.resize(p0 + h[1]);
+      st.pending_pay.resize((p0 + h[1]) * lb);
+      STEP(hipMemcpy(st.pending.data() + p0, b_pend.p, h[1] * sizeof(cvx::StrokeItem),
+                     hipMemcpyDeviceToHost));
+      STEP(hipMemcpy(st.pending_pay.data() + p0 * lb, b_ppay.p, (size_t)h[1] * lb,
+                     hipMemcpyDeviceToHost));
+    }
+    std::swap(b_cur.p, b_next.p);
+    n = h[0];
+  }
+#undef STEP
+  if (e != hipSuccess) return hip_fail(ctx, e, where);
+  return CVX_OK;
+}
+
+int stroke_step_impl(cvx_ctx* ctx, DevCanvas& c, uint64_t* pending) {
+  cvx::StrokeState& st = c.stroke;
+  if (!st.active || st.pending.empty()) {
+    st = cvx::StrokeState();
+    if (pending) *pending = 0;
+    return CVX_OK;
+  }
+  const uint32_t fmt = c.desc.leaf_format, lb = leaf_bytes(fmt);
+  const size_t n = st.pending.size();
+  if (n > 0xffffffffull / 8) {
+    st = cvx::StrokeState();
+    return fail(ctx, CVX_ERR_INVALID_ARG, "too many leaves waiting for a split");
+  }
+  // splits in ascending node order, so that the ids the children get do not
+  // depend on the order in which the GPU appended the waiting leaves
+  std::vector<uint32_t> ord(n);
+  for (size_t i = 0; i < n; ++i) ord[i] = (uint32_t)i;
+  std::sort(ord.begin(), ord.end(),
+            [&](uint32_t a, uint32_t b) { return st.pending[a].node < st.pending[b].node; });
+  std::vector<cvx_edit> edits(n);
+  std::vector<uint8_t> pays(n * 8 * lb);
+  for (size_t i = 0; i < n; ++i) {
+    edits[i].op = CVX_EDIT_REFINE;
+    edits[i].node = st.pending[ord[i]].node;
+    edits[i].first_payload = 8 * (uint64_t)i;
+    uint8_t cp[32];
+    child_payload(st.pending_pay.data() + (size_t)ord[i] * lb, fmt, cp);
+    for (uint32_t o = 0; o < 8; ++o) std::memcpy(pays.data() + (8 * i + o) * lb, cp, lb);
+  }
+  std::vector<uint32_t> first(n);
+  int rc = edit_impl(ctx, c, edits.data(), (uint32_t)n, pays.data(), 8 * (uint64_t)n,
+                     first.data());
+  if (rc != CVX_OK) {
+    st = cvx::StrokeState();
+    return rc;
+  }
+  std::vector<cvx::StrokeItem> kids(8 * n);
+  for (size_t i = 0; i < n; ++i) {
+    const cvx::StrokeItem& p = st.pending[ord[i]];
+    for (uint32_t o = 0; o < 8; ++o) {
+      cvx::StrokeItem& k = kids[8 * i + o];
+      k = cvx::StrokeItem{};
+      k.node = first[i] + o;
+      k.x = 2 * p.x + (o & 1u);
+      k.y = 2 * p.y + ((o >> 1) & 1u);
+      k.z = 2 * p.z + ((o >> 2) & 1u);
+      k.depth = p.depth + 1;
+    }
+  }
+  st.pending.clear();
+  st.pending_pay.clear();
+  rc = stroke_walk(ctx, c, &kids);
+  if (rc != CVX_OK) {
+    st = cvx::StrokeState();
+    return rc;
+  }
+  if (st.pending.empty()) st = cvx::StrokeState();
+  if (pending) *pending = st.pending.size();
+  return CVX_OK;
+}
+
+}  // namespace
+
+int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, const double* stamps,
+                     uint32_t n_stamps, uint64_t* pending) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  DevCanvas& c = ctx->canvases[canvas_id];
+  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  if (!stroke) return fail(ctx, CVX_ERR_INVALID_ARG, "stroke is NULL");
+  if (n_stamps < 1 || n_stamps > CVX_MAX_STAMPS || !stamps)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "n_stamps must be in [1, CVX_MAX_STAMPS]");
+  for (int k = 0; k < 3; ++k)
+    if (!(stroke->rgb[k] >= 0.0 && stroke->rgb[k] <= 1.0))
+      return fail(ctx, CVX_ERR_INVALID_ARG, "stroke colour outside [0, 1]");
+  if (!(std::isfinite(stroke->sigma) && stroke->sigma >= 0.0))
+    return fail(ctx, CVX_ERR_INVALID_ARG, "stroke sigma must be finite and >= 0");
+  if (!(std::isfinite(stroke->radius) && stroke->radius > 0.0))
+    return fail(ctx, CVX_ERR_INVALID_ARG, "stroke radius must be finite and > 0");
+  if (!(std::isfinite(stroke->k_refine) && stroke->k_refine > 0.0))
+    return fail(ctx, CVX_ERR_INVALID_ARG, "stroke k_refine must be finite and > 0");
+  for (uint64_t j = 0; j < 4ull * n_stamps; ++j)
+    if (!std::isfinite(stamps[j]) || (j % 4 == 3 && stamps[j] < 0.0))
+      return fail(ctx, CVX_ERR_INVALID_ARG,
+                  "stamp " + std::to_string(j / 4) + " not finite or with r < 0");
+  CVX_HIP(hipSetDevice(ctx->device));
+  // a stroke still in progress is completed first (at most one level per step)
+  for (uint32_t guard = 0; c.stroke.active && guard <= 64; ++guard) {
+    int rc = stroke_step_impl(ctx, c, nullptr);
+    if (rc != CVX_OK) return rc;
+  }
+  CVX_HIP(hipStreamSynchronize(ctx->stream));
+  cvx::StrokeState st;
+  for (int k = 0; k < 3; ++k) {
+    st.args.origin[k] = c.desc.origin[k];
+    st.args.rgb[k] = stroke->rgb[k];
+  }
+  st.args.root_edge = c.desc.root_edge;
+  st.args.sigma = stroke->sigma;
+  st.args.radius = stroke->radius;
+  st.args.hmin = stroke->radius / stroke->k_refine;
+  st.args.R = c.desc.R;
+  st.args.max_depth = c.desc.max_depth;
+  st.args.fmt = c.desc.leaf_format;
+  st.args.n_stamps = n_stamps;
+  st.stamps.assign(stamps, stamps + 4ull * n_stamps);
+  st.active = true;
+  c.stroke = std::move(st);
+  int rc = stroke_walk(ctx, c, nullptr);
+  if (rc != CVX_OK) {
+    c.stroke = cvx::StrokeState();
+    return rc;
+  }
+  if (c.stroke.pending.empty()) c.stroke = cvx::StrokeState();
+  if (pending) *pending = c.stroke.pending.size();
+  return CVX_OK;
+}
+
+int cvx_stroke_step(cvx_ctx* ctx, int canvas_id, uint64_t* pending) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (canvas_id < 0 || canvas_id >= CVX_MAX_CANVASES)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "canvas_id out of range");
+  DevCanvas& c = ctx->canvases[canvas_id];
+  if (!c.present) return fail(ctx, CVX_ERR_NOT_FOUND, "no pool under canvas_id");
+  CVX_HIP(hipSetDevice(ctx->device));
+  CVX_HIP(hipStreamSynchronize(ctx->stream));
+  return stroke_step_impl(ctx, c, pending);
 }
 
 int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,

@@ -32,6 +32,32 @@ int validate_views(const cvx_view* views, int n_views, const cvx_canvas_desc* co
 //            depth across the face of the parent that this child touches, or
 //            the coarser leaf covering it; CVX_NONE outside the canvas or for roots.
 // Payload (indexed by node id): RGBA8 + half kappa (uint2) or 4 doubles.
+// A cell on the walk of a brush stroke: node id, integer coordinates at its
+// depth (root array at depth 0), depth.
+struct StrokeItem {
+  uint32_t node, x, y, z, depth, pad0, pad1, pad2;
+};
+
+// One stroke in device-ready form (world units, as the canvas descriptor).
+struct StrokeArgs {
+  double origin[3];
+  double root_edge;
+  double rgb[3];
+  double sigma, radius, hmin;  // hmin = radius / k_refine
+  uint32_t R, max_depth, fmt, n_stamps;
+};
+
+// A stroke whose splits are still being applied, one level per step: its
+// parameters and stamps, and the leaves waiting for a split with their
+// payloads from before the stroke.
+struct StrokeState {
+  bool active = false;
+  StrokeArgs args{};
+  std::vector<double> stamps;  // 4 per stamp: x, y, z, r
+  std::vector<StrokeItem> pending;
+  std::vector<uint8_t> pending_pay;
+};
+
 struct DevCanvas {
   bool present = false;
   cvx_canvas_desc desc{};
@@ -54,6 +80,7 @@ struct DevCanvas {
   uint32_t* mark = nullptr;  // per node: last edit call whose link rebuild visited it
   uint64_t mark_cap = 0;
   uint32_t epoch = 0;
+  StrokeState stroke;
 };
 
 // Depth of the top-level table of a canvas: at most 6 levels and 2^18 cells,
@@ -143,5 +170,10 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
 int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out_f64,
                 const CastArgs& a, uint32_t workgroups, uint32_t wg_size);
 int launch_reset(void* stream, CastHeader* hdr);
+// one level of a stroke's walk (cvx_stroke.hip); items == nullptr: the roots
+int launch_stroke_visit(void* stream, const StrokeItem* items, uint32_t n, const StrokeArgs& a,
+                        const void* stamps, const void* rec, void* pay, uint64_t n_nodes,
+                        StrokeItem* next, uint32_t* next_count, uint32_t next_cap,
+                        StrokeItem* pend, void* pend_pay, uint32_t* pend_count, uint32_t pend_cap);
 
 }  // namespace cvx

@@ -47,12 +47,18 @@ CVX_STAT_COUNT = 8
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",
             "cvx_last_error", "cvx_status_str", "cvx_validate_pool", "cvx_validate_views",
             "cvx_pool_bytes", "cvx_autotune", "cvx_edit_pool", "cvx_pool_nodes",
-            "cvx_read_records"]
+            "cvx_read_records", "cvx_read_payloads", "cvx_stroke_begin", "cvx_stroke_step"]
 
 CVX_EDIT_PAINT = 0
 CVX_EDIT_REFINE = 1
 CVX_EDIT_COARSEN = 2
 CVX_NONE_ID = 0xFFFFFFFF
+CVX_MAX_STAMPS = 65536
+
+
+class cvx_stroke(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_double * 3), ("sigma", ctypes.c_double),
+                ("radius", ctypes.c_double), ("k_refine", ctypes.c_double)]
 
 
 class cvx_canvas_desc(ctypes.Structure):
@@ -133,6 +139,10 @@ _lib.cvx_pool_bytes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint6
 _lib.cvx_edit_pool.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, ctypes.c_uint64, _vp]
 _lib.cvx_pool_nodes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
 _lib.cvx_read_records.argtypes = [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, _vp]
+_lib.cvx_read_payloads.argtypes = [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, _vp]
+_lib.cvx_stroke_begin.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(cvx_stroke), _vp,
+                                  ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+_lib.cvx_stroke_step.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
 _lib.cvx_autotune.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(cvx_render_opts),
                               ctypes.c_uint32, ctypes.POINTER(cvx_render_opts),
                               ctypes.POINTER(cvx_tune_result), ctypes.c_uint32,
@@ -252,6 +262,39 @@ def cvx_read_records(ctx, canvas_id, first=0, count=None):
     _check(ctx, _lib.cvx_read_records(ctx, int(canvas_id), int(first), int(count),
                                       out.ctypes.data if count else None))
     return out
+
+
+def cvx_read_payloads(ctx, canvas_id, dtype, first=0, count=None):
+    """Device leaf payloads indexed by node id, as an array of the pool's leaf
+    dtype (diagnostic; entries of non-leaf ids are unspecified)."""
+    if count is None:
+        count = cvx_pool_nodes(ctx, canvas_id) - first
+    out = np.zeros(count, dtype)
+    _check(ctx, _lib.cvx_read_payloads(ctx, int(canvas_id), int(first), int(count),
+                                       out.ctypes.data if count else None))
+    return out
+
+
+def cvx_stroke_begin(ctx, canvas_id, stamps, rgb, sigma, radius, k_refine) -> int:
+    """Start a brush stroke (stamps: (n, 4) x, y, z, r in world units); returns
+    the number of leaves waiting for a split."""
+    st = cvx_stroke()
+    st.rgb[:] = [float(v) for v in rgb]
+    st.sigma, st.radius, st.k_refine = float(sigma), float(radius), float(k_refine)
+    arr = np.ascontiguousarray(stamps, np.float64).reshape(-1, 4)
+    pend = ctypes.c_uint64()
+    _check(ctx, _lib.cvx_stroke_begin(ctx, int(canvas_id), ctypes.byref(st),
+                                      arr.ctypes.data if len(arr) else None, len(arr),
+                                      ctypes.byref(pend)))
+    return int(pend.value)
+
+
+def cvx_stroke_step(ctx, canvas_id) -> int:
+    """One deferred level of the stroke in progress; returns the leaves still
+    waiting for a split (0: the stroke is complete)."""
+    pend = ctypes.c_uint64()
+    _check(ctx, _lib.cvx_stroke_step(ctx, int(canvas_id), ctypes.byref(pend)))
+    return int(pend.value)
 
 
 def cvx_free_pool(ctx, canvas_id):

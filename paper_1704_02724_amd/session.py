@@ -49,6 +49,17 @@ class Session:
         self.torch.cuda.current_stream(self.device).synchronize()
         return cvx.cvx_edit_pool(self.ctx, canvas_id, edits, payloads)
 
+    def stroke_begin(self, canvas_id, stamps, rgb, sigma, radius, k_refine):
+        """Paint a brush stroke into the existing leaves (cvx_stroke_begin);
+        returns the number of leaves waiting for a split."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return cvx.cvx_stroke_begin(self.ctx, canvas_id, stamps, rgb, sigma, radius, k_refine)
+
+    def stroke_step(self, canvas_id):
+        """One deferred refinement level of the stroke (cvx_stroke_step)."""
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return cvx.cvx_stroke_step(self.ctx, canvas_id)
+
     def free(self, canvas_id):
         cvx.cvx_free_pool(self.ctx, canvas_id)
         self.descs.pop(canvas_id, None)

@@ -1,0 +1,218 @@
+"""GPU brush strokes (cvx_stroke_begin / cvx_stroke_step) against the stroke
+oracle: the immediate pass paints exactly the oracle's leaves and leaves the
+oracle's cells waiting; the deferred steps end, within max-depth steps, on
+the oracle's canvas for the stroke applied at once (FP64 leaves bit-exact;
+RGBA8 leaves bit-exact but for the A byte, which is within one unit because
+exp rounds differently on the two sides); the edited device pool holds the
+records of a fresh upload of the same tree and renders like the oracle on
+it.  Argument errors change nothing; an edit drops a stroke in progress; a
+new stroke completes the previous one first."""
+import numpy as np
+import pytest
+
+from canvasgen import LEAF_F64, LEAF_RGBA8_F16, make_view, trees
+from canvasgen.pool import LEAF, LEAF_DTYPE, NONE, Canvas, build_from_strokes
+from canvasgen.strokes import StrokeSet, gen_strokes
+from oracle import oracle
+from oracle import stroke as so
+
+from gpu_common import all_ray_ids, compare_traces, rgba_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sess():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_02724_amd.session import Session
+    s = Session(0)
+    yield s
+    s.close()
+
+
+def _subset(st, n):
+    return StrokeSet(st.radius[:n], st.rgb[:n], st.sigma[:n], st.stamp_off[:n + 1],
+                     st.stamps[:st.stamp_off[n]])
+
+
+def _device_pool(sess, cid, cv):
+    """The device pool as a host canvas (leaves indexed by node id) and as
+    the oracle's canonical leaf dict."""
+    from paper_1704_02724_amd import cvx
+    rec = cvx.cvx_read_records(sess.ctx, cid)
+    pay = cvx.cvx_read_payloads(sess.ctx, cid, LEAF_DTYPE[cv.leaf_format])
+    n = len(rec)
+    nodes = np.empty((n, 2), np.uint32)
+    nodes[:, 0] = LEAF
+    nodes[:, 1] = NONE
+    leaves = {}
+    R = cv.R
+    stack = [(i, 0, i % R, (i // R) % R, i // (R * R)) for i in range(R ** 3)]
+    while stack:
+        i, d, x, y, z = stack.pop()
+        w = int(rec[i, 0])
+        if w & 1:
+            assert (w >> 1) & 63 == d
+            nodes[i, 0] = LEAF | i
+            leaves[(d, x, y, z)] = tuple(pay[i].tolist())
+        else:
+            nodes[i, 0] = w
+            for o in range(8):
+                nodes[w + o, 1] = i
+                stack.append((w + o, d + 1, 2 * x + (o & 1), 2 * y + ((o >> 1) & 1),
+                              2 * z + ((o >> 2) & 1)))
+    # payload slots of ids that are not leaves hold no record: zero them
+    arr = np.zeros(n, LEAF_DTYPE[cv.leaf_format])
+    is_leaf = (nodes[:, 0] & LEAF) != 0
+    arr[is_leaf] = pay[is_leaf]
+    host = Canvas(nodes, arr, cv.R, cv.max_depth, cv.leaf_format, origin=cv.origin,
+                  root_edge=cv.root_edge)
+    return host, leaves
+
+
+def _same_leaves(got, want, fmt):
+    assert set(got) == set(want)
+    if fmt == LEAF_F64:
+        bad = [c for c in want if got[c] != want[c]]
+    else:
+        bad = [c for c in want if got[c][:3] + got[c][4:] != want[c][:3] + want[c][4:]
+               or abs(got[c][3] - want[c][3]) > 1]
+    assert not bad, (len(bad), [(c, got[c], want[c]) for c in bad[:3]])
+
+
+def _stroke_args(cv, st, i, k):
+    return (cv.R, cv.max_depth, cv.root_edge, cv.origin, st.stamps_of(i), st.rgb[i],
+            st.sigma[i], st.radius[i], k)
+
+
+def _views(rng, n, W, H):
+    vs, off = [], 0
+    for _ in range(n):
+        e = rng.uniform(0.05, 0.95, 3)
+        tgt = rng.uniform(0.2, 0.8, 3)
+        vs.append(make_view(e, tgt - e, rng.uniform(0.4, 1.2), W, H, out_offset_px=off))
+        off += W * H
+    return vs
+
+
+@pytest.mark.parametrize("R,D,n,lg,fmt,seed", [
+    (1, 9, 4, (-7, -4), LEAF_F64, 91),
+    (2, 8, 4, (-7, -4), LEAF_RGBA8_F16, 92),
+    (1, 12, 3, (-10, -6), LEAF_RGBA8_F16, 93),
+])
+def test_strokes_match_oracle(sess, R, D, n, lg, fmt, seed):
+    from paper_1704_02724_amd import cvx
+    k = 4.0
+    st = gen_strokes(np.random.Generator(np.random.PCG64(seed)), n + 2, *lg)
+    cv = build_from_strokes(_subset(st, n), R, D, k, fmt)
+    sess.upload(0, cv)
+    want = so.canonical_from_pool(cv.nodes, cv.leaves, R)
+    for i in (n, n + 1):
+        args = _stroke_args(cv, st, i, k)
+        imm, pend = so.immediate(want, fmt, *args)
+        print(f"stroke {i}: {len(pend)} leaves waiting", flush=True)
+        got_pend = sess.stroke_begin(0, st.stamps_of(i), st.rgb[i], st.sigma[i], st.radius[i], k)
+        assert got_pend == len(pend)
+        _same_leaves(_device_pool(sess, 0, cv)[1], imm, fmt)
+        want, split = so.apply_stroke(want, fmt, *args)
+        steps = 0
+        while got_pend:
+            got_pend = sess.stroke_step(0)
+            steps += 1
+            assert steps <= D
+        assert (steps > 0) == (len(pend) > 0)
+        host, got = _device_pool(sess, 0, cv)
+        _same_leaves(got, want, fmt)
+    assert cvx.cvx_stroke_step(sess.ctx, 0) == 0          # nothing in progress
+    # the edited pool: records of a fresh upload, and the oracle's image
+    sess.upload(1, host)
+    np.testing.assert_array_equal(cvx.cvx_read_records(sess.ctx, 0),
+                                  cvx.cvx_read_records(sess.ctx, 1))
+    views = _views(np.random.Generator(np.random.PCG64(seed)), 2, 32, 24)
+    variant, tol = ("fp64_plain", 1e-6) if fmt == LEAF_F64 else ("fp32_rebased", 1e-3)
+    ids = all_ray_ids(views)
+    orc = oracle.render([host], views, ids, max_leaves=1024)
+    gpu = sess.trace(views, ids, 1024, variant)
+    cmp = compare_traces(orc, gpu, 1024)
+    assert cmp["seq_mismatch"] == 0, cmp
+    img = sess.render(views, variant).cpu().numpy()
+    assert rgba_err(img, orc["rgba"], cmp["ok_mask"]) <= tol
+
+
+@pytest.mark.parametrize("fmt", [LEAF_F64, LEAF_RGBA8_F16])
+def test_stroke_into_a_coarse_canvas(sess, fmt):
+    """A depth-3 canvas with room for depth 9 and strokes of radius 2^-6:
+    many leaves wait at once and the splits take four steps (depth 3 to 7)."""
+    rng = np.random.Generator(np.random.PCG64(95))
+    cv = trees.from_refinement(2, 9, lambda d, c: d < 3,
+                               lambda d, c: (*rng.uniform(0, 1, 3), rng.uniform(0.0, 2.0)), fmt)
+    k = 4.0
+    st = gen_strokes(np.random.Generator(np.random.PCG64(96)), 2, -6, -6)
+    sess.upload(0, cv)
+    want = so.canonical_from_pool(cv.nodes, cv.leaves, cv.R)
+    for i in range(st.n):
+        args = _stroke_args(cv, st, i, k)
+        imm, pend = so.immediate(want, fmt, *args)
+        p = sess.stroke_begin(0, st.stamps_of(i), st.rgb[i], st.sigma[i], st.radius[i], k)
+        assert p == len(pend) and p > 8
+        _same_leaves(_device_pool(sess, 0, cv)[1], imm, fmt)
+        want, split = so.apply_stroke(want, fmt, *args)
+        counts = [p]
+        while p:
+            p = sess.stroke_step(0)
+            counts.append(p)
+        print(f"stroke {i}: waiting leaves per step {counts}, {len(split)} splits", flush=True)
+        assert len(counts) - 1 == len({c[0] for c in split})   # one level per step
+        assert sum(counts) == len(split)
+        _same_leaves(_device_pool(sess, 0, cv)[1], want, fmt)
+
+
+def test_stroke_errors_edits_and_overlap(sess):
+    from paper_1704_02724_amd import cvx
+    k = 4.0
+    fmt = LEAF_RGBA8_F16
+    st = gen_strokes(np.random.Generator(np.random.PCG64(94)), 4, -7, -4)
+    cv = build_from_strokes(_subset(st, 2), 1, 9, k, fmt)
+    sess.upload(0, cv)
+    base = cvx.cvx_read_payloads(sess.ctx, 0, LEAF_DTYPE[fmt])
+    good = st.stamps_of(2)
+    bad_args = [
+        (np.zeros((0, 4)), st.rgb[2], 1.0, 0.01),               # no stamps
+        (good, (1.5, 0.0, 0.0), 1.0, 0.01),                     # colour outside [0, 1]
+        (good, st.rgb[2], -1.0, 0.01),                          # sigma < 0
+        (good, st.rgb[2], 1.0, 0.0),                            # radius 0
+        (np.where(np.arange(good.size).reshape(good.shape) == 5, np.nan, good),
+         st.rgb[2], 1.0, 0.01),                                 # NaN stamp
+    ]
+    for stamps, rgb, sigma, radius in bad_args:
+        with pytest.raises(cvx.CvxError) as e:
+            sess.stroke_begin(0, stamps, rgb, sigma, radius, k)
+        assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+    np.testing.assert_array_equal(cvx.cvx_read_payloads(sess.ctx, 0, LEAF_DTYPE[fmt]), base)
+    # a stroke that misses the canvas changes nothing
+    far = good.copy()
+    far[:, :3] += 5.0
+    assert sess.stroke_begin(0, far, st.rgb[2], st.sigma[2], st.radius[2], k) == 0
+    np.testing.assert_array_equal(cvx.cvx_read_payloads(sess.ctx, 0, LEAF_DTYPE[fmt]), base)
+    # an edit drops the stroke in progress: its splits never happen
+    start = so.canonical_from_pool(cv.nodes, cv.leaves, 1)
+    args = _stroke_args(cv, st, 2, k)
+    imm, pend = so.immediate(start, fmt, *args)
+    assert len(pend) > 0
+    assert sess.stroke_begin(0, good, st.rgb[2], st.sigma[2], st.radius[2], k) == len(pend)
+    sess.edit(0, np.zeros(0, cvx.EDIT_DTYPE), np.zeros(0, LEAF_DTYPE[fmt]))
+    assert cvx.cvx_stroke_step(sess.ctx, 0) == 0
+    _same_leaves(_device_pool(sess, 0, cv)[1], imm, fmt)
+    # a new stroke completes the previous one first: two overlapping strokes
+    # begun back to back end on the oracle's sequential result
+    sess.upload(0, cv)
+    after2, _ = so.apply_stroke(start, fmt, *args)
+    args3 = _stroke_args(cv, st, 3, k)
+    want, _ = so.apply_stroke(after2, fmt, *args3)
+    sess.stroke_begin(0, good, st.rgb[2], st.sigma[2], st.radius[2], k)
+    p = sess.stroke_begin(0, st.stamps_of(3), st.rgb[3], st.sigma[3], st.radius[3], k)
+    while p:
+        p = sess.stroke_step(0)
+    _same_leaves(_device_pool(sess, 0, cv)[1], want, fmt)

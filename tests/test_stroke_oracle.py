@@ -1,0 +1,139 @@
+"""CPU pins of the stroke oracle (oracle/stroke.py).
+
+* Against the canvas builder, an independent implementation of the same
+  painting rules that applies strokes in sequence: painting stroke n into the
+  builder's canvas of strokes 1..n-1 gives exactly (FP64 leaves) the builder's
+  canvas of strokes 1..n, for several seeds, root arrays and depths.
+* Brute-force properties: after a stroke every leaf the stamps overlap is at
+  the brush resolution or the max depth; every leaf they miss is unchanged;
+  the leaves still tile the canvas.
+* The RGBA8 + half-kappa path equals the FP64 path encoded, on a canvas whose
+  payloads both formats hold exactly (every leaf the stroke changes; the rest
+  are untouched in both).
+* The deferred passes (immediate paint, then one level of splits at a time)
+  end on the result of the stroke applied at once.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from canvasgen import LEAF_F64, LEAF_RGBA8_F16, trees
+from canvasgen.pool import build_from_strokes
+from canvasgen.strokes import StrokeSet, gen_strokes
+from oracle import stroke as so
+
+
+def _subset(st, n):
+    return StrokeSet(st.radius[:n], st.rgb[:n], st.sigma[:n], st.stamp_off[:n + 1],
+                     st.stamps[:st.stamp_off[n]])
+
+
+def _canon(cv):
+    return so.canonical_from_pool(cv.nodes, cv.leaves, cv.R)
+
+
+def _apply(cv, st, i, k, leaves=None, fmt=None):
+    return so.apply_stroke(_canon(cv) if leaves is None else leaves,
+                           cv.leaf_format if fmt is None else fmt, cv.R, cv.max_depth,
+                           cv.root_edge, cv.origin, st.stamps_of(i), st.rgb[i], st.sigma[i],
+                           st.radius[i], k)
+
+
+@pytest.mark.parametrize("R,D,n,lg,seed", [(1, 8, 6, (-6, -3), 1), (2, 7, 5, (-6, -3), 2),
+                                          (1, 10, 4, (-9, -5), 3), (3, 6, 8, (-5, -2), 4)])
+def test_stroke_matches_sequential_builder(R, D, n, lg, seed):
+    k = 4.0
+    st = gen_strokes(np.random.Generator(np.random.PCG64(seed)), n, *lg)
+    prev = build_from_strokes(_subset(st, n - 1), R, D, k, LEAF_F64)
+    full = build_from_strokes(st, R, D, k, LEAF_F64)
+    got, split = _apply(prev, st, n - 1, k)
+    want = _canon(full)
+    assert set(got) == set(want)
+    bad = [c for c in want if got[c] != want[c]]
+    assert not bad, (len(bad), bad[:3])
+    # the last stroke changed something and split something
+    before = _canon(prev)
+    assert split and any(before.get(c) != v for c, v in want.items())
+
+
+def test_stroke_properties_brute_force():
+    rng = np.random.Generator(np.random.PCG64(11))
+    cv = trees.random_tree(2, 6, seed=11, max_nodes=4000, leaf_format=LEAF_F64)
+    before = _canon(cv)
+    st = gen_strokes(rng, 3, -5, -3)
+    k = 4.0
+    for i in range(st.n):
+        after, _ = _apply(cv, st, i, k, leaves=before)
+        stamps = st.stamps_of(i)
+        hmin = st.radius[i] / k
+        vol = 0.0
+        for (d, x, y, z), pay in after.items():
+            e = math.ldexp(cv.root_edge, -d)
+            lo = np.array([x, y, z], np.float64) * e
+            near = np.maximum(np.maximum(lo[None, :] - stamps[:, :3], 0.0),
+                              stamps[:, :3] - (lo[None, :] + e))
+            overlap = np.any((near * near).sum(1) < stamps[:, 3] ** 2)
+            if overlap:
+                assert e <= hmin or d == cv.max_depth
+            vol += 8.0 ** -d
+        assert vol == pytest.approx(cv.R ** 3)
+        for cell, pay in before.items():
+            d, x, y, z = cell
+            e = math.ldexp(cv.root_edge, -d)
+            lo = np.array([x, y, z], np.float64) * e
+            near = np.maximum(np.maximum(lo[None, :] - stamps[:, :3], 0.0),
+                              stamps[:, :3] - (lo[None, :] + e))
+            if not np.any((near * near).sum(1) < stamps[:, 3] ** 2):
+                assert after[cell] == pay
+        before = after
+
+
+def test_rgba8_path_is_the_f64_path_encoded():
+    cv8 = trees.random_tree(1, 6, seed=12, max_nodes=3000, leaf_format=LEAF_RGBA8_F16,
+                            kappa_range=(0.0, 4.0))
+    leaves8 = _canon(cv8)
+    leaves64 = {c: so.decode(p, so.RGBA8_F16) for c, p in leaves8.items()}
+    st = gen_strokes(np.random.Generator(np.random.PCG64(12)), 4, -5, -3)
+    for i in range(st.n):
+        a8, s8 = _apply(cv8, st, i, 4.0, leaves=leaves8, fmt=so.RGBA8_F16)
+        a64, s64 = _apply(cv8, st, i, 4.0, leaves=leaves64, fmt=so.F64)
+        assert s8 == s64 and set(a8) == set(a64)
+        for c in a8:
+            if leaves8.get(c) == a8[c]:          # untouched (its A byte is the generator's)
+                assert a64[c] == leaves64[c], c
+            else:
+                assert a8[c] == so.encode(a64[c], so.RGBA8_F16), c
+        leaves8 = a8
+        leaves64 = {c: so.decode(p, so.RGBA8_F16) for c, p in a8.items()}
+
+
+@pytest.mark.parametrize("fmt", [LEAF_F64, LEAF_RGBA8_F16])
+def test_deferred_passes_end_on_the_stroke_at_once(fmt):
+    """Immediate paint of the existing leaves, then one level of splits per
+    pass whose children start from the payload before the stroke."""
+    cv = trees.random_tree(1, 7, seed=13, max_nodes=2000, leaf_format=fmt)
+    st = gen_strokes(np.random.Generator(np.random.PCG64(13)), 2, -7, -4)
+    k = 4.0
+    for i in range(st.n):
+        start = _canon(cv)
+        want, _ = _apply(cv, st, i, k, leaves=start)
+        args = (cv.R, cv.max_depth, cv.root_edge, cv.origin, st.stamps_of(i), st.rgb[i],
+                st.sigma[i], st.radius[i], k)
+        cur, pending = so.immediate(start, fmt, *args)
+        pre = {c: start[c] for c in pending}
+        passes = 0
+        while pending:
+            passes += 1
+            kids = {}
+            for (d, x, y, z) in pending:
+                del cur[(d, x, y, z)]
+                cp = so.child_payload(pre[(d, x, y, z)], fmt)
+                for o in range(8):
+                    kids[(d + 1, 2 * x + (o & 1), 2 * y + ((o >> 1) & 1),
+                          2 * z + ((o >> 2) & 1))] = cp
+            painted, pending = so.immediate(kids, fmt, *args)
+            pre = {c: kids[c] for c in pending}
+            cur.update(painted)
+        assert 0 < passes <= cv.max_depth
+        assert cur == want
