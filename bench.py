@@ -195,6 +195,34 @@ def edit_bench(sess, cv, n_paint, n_refine, n_coarsen, seed):
                 nodes=int(cv.n_nodes))
 
 
+def stroke_bench(sess, cv, seed):
+    """Times brush strokes with deferred refinement (cvx_stroke_begin, then one
+    cvx_stroke_step per frame until no leaf waits) on a copy of the canvas:
+    seeded strokes of a fine, a middle and a large brush radius."""
+    from canvasgen.strokes import gen_strokes
+    torch = sess.torch
+    sess.upload(9, cv)
+    torch.cuda.synchronize()
+    out = []
+    for j, lg in enumerate((-16, -10, -5)):
+        st = gen_strokes(np.random.Generator(np.random.PCG64(seed + j)), 1, lg, lg)
+        t = time.perf_counter()
+        p = sess.stroke_begin(9, st.stamps_of(0), st.rgb[0], st.sigma[0], st.radius[0], 4.0)
+        frames = [round((time.perf_counter() - t) * 1e3, 2)]
+        waiting = [p]
+        while p:
+            t = time.perf_counter()
+            p = sess.stroke_step(9)
+            frames.append(round((time.perf_counter() - t) * 1e3, 2))
+            waiting.append(p)
+        row = dict(radius_log2=lg, stamps=int(len(st.stamps_of(0))), frame_ms=frames,
+                   waiting=waiting, splits=int(sum(waiting)))
+        log(f"stroke: {row}")
+        out.append(row)
+    sess.free(9)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,7 +242,7 @@ def main():
                     help="use --tile/--workgroups/--wg-size instead of cvx_autotune's pick")
     ap.add_argument("--tune-reps", type=int, default=3)
     ap.add_argument("--edit-bench", type=int, default=1,
-                    help="also time one batch of pool edits on the first canvas (0 skips it)")
+                    help="also time pool edits and brush strokes on the first canvas (0 skips them)")
     ap.add_argument("--per-view-steps", type=int, default=-1,
                     help="steps of the one-launch-per-view comparison (default 3 when the "
                          "workload has more than two views; 0 skips it)")
@@ -350,6 +378,7 @@ def main():
     if args.edit_bench:
         edit = edit_bench(sess, cv[0], 20000, 2000, 500, 99)
         log(f"pool edits: {edit}")
+        edit["strokes"] = stroke_bench(sess, cv[0], 123)
 
     # --- CPU oracle baseline on a bounded sample
     cpu = None
