@@ -19,14 +19,14 @@ using cvx::DView;
 
 struct GraphKey {
   uint32_t variant = ~0u, tw = 0, th = 0, wgs = 0, wg = 0;
-  bool trace = false, stats = false, out64 = false;
+  bool trace = false, stats = false, out64 = false, small = false;
   const void* out = nullptr;
   const void* stats_ptr = nullptr;
   const void* views = nullptr;
   bool operator==(const GraphKey& o) const {
     return variant == o.variant && tw == o.tw && th == o.th && wgs == o.wgs && wg == o.wg &&
-           trace == o.trace && stats == o.stats && out64 == o.out64 && out == o.out &&
-           stats_ptr == o.stats_ptr && views == o.views;
+           trace == o.trace && stats == o.stats && out64 == o.out64 && small == o.small &&
+           out == o.out && stats_ptr == o.stats_ptr && views == o.views;
   }
 };
 
@@ -416,6 +416,9 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   a.stats = o.stats;
   a.tile_w = tw;
   a.tile_h = th;
+  a.small_pools = 1;
+  for (int i = 0; i < n_views; ++i)
+    if (ctx->canvases[views[i].canvas_id].n_nodes > (1ull << 28)) a.small_pools = 0;
   if (tr) {
     a.ray_ids = tr->ray_ids;
     a.max_leaves = tr->max_leaves;
@@ -444,6 +447,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   key.trace = false;
   key.stats = stats;
   key.out64 = o.out_f64 != 0;
+  key.small = a.small_pools != 0;
   key.out = out_dev;
   key.stats_ptr = o.stats;
   key.views = ctx->d_views;

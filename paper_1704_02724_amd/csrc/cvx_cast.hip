@@ -29,6 +29,10 @@
 
 #include "cvx_internal.h"
 
+#ifndef CVX_CAST32_WAVES
+#define CVX_CAST32_WAVES 8
+#endif
+
 namespace cvx {
 
 namespace {
@@ -149,6 +153,21 @@ __device__ __forceinline__ uint4 ld_rec(const void* rec, uint32_t i) {
 }
 __device__ __forceinline__ uint2 ld_pay(const void* pay, uint32_t i) {
   const u32x2_t x = ((gpay_t)pay)[i];
+  return make_uint2(x.x, x.y);
+}
+// The same with a 32-bit byte offset from the (uniform) base, for pools of at
+// most 2^28 nodes: the loads take the scalar-base form and the per-step
+// 64-bit address arithmetic goes away.
+template <bool SMALL>
+__device__ __forceinline__ uint4 ld_rec_t(const void* rec, uint32_t i) {
+  if constexpr (!SMALL) return ld_rec(rec, i);
+  const u32x4_t x = *(grec_t)((const __attribute__((address_space(1))) char*)rec + (i << 4));
+  return make_uint4(x.x, x.y, x.z, x.w);
+}
+template <bool SMALL>
+__device__ __forceinline__ uint2 ld_pay_t(const void* pay, uint32_t i) {
+  if constexpr (!SMALL) return ld_pay(pay, i);
+  const u32x2_t x = *(gpay_t)((const __attribute__((address_space(1))) char*)pay + (i << 3));
   return make_uint2(x.x, x.y);
 }
 
@@ -358,7 +377,7 @@ struct RaySlot {
   __device__ __forceinline__ double at(int j) const { return opaque(p)[j * stride]; }
 };
 
-template <bool TRACE, bool STATS>
+template <bool TRACE, bool STATS, bool SMALL>
 __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& o,
                           const V3<double>& d, const Entry& en, const V3<bool>& up, Sink sk,
                           Acc& acc, Out& out) {
@@ -403,7 +422,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     bad = bad || !descend_int(rec, v.n_nodes, deep_coords(q, up, v.R, v.max_depth), v.max_depth,
                               I, dep, c, r);
     if (STATS) acc.descent += dep - d0;
-    pay = ld_pay(payp, I);
+    pay = ld_pay_t<SMALL>(payp, I);
     db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
     w = 1u << (db - dep);
     const double hd = ldexp(1.0, -(int)dep);
@@ -432,8 +451,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   const uint32_t ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
   uint32_t step = 0;
   for (;; ++step) {
-    if (step >= v.max_steps) { out.flags |= CVX_RAYFLAG_STEP_CAP; break; }
-    if (bad) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
+    if (step >= v.max_steps || bad) {
+      out.flags |= bad ? CVX_RAYFLAG_BAD_LINK : CVX_RAYFLAG_STEP_CAP;
+      break;
+    }
     // s-values of the far planes (leaf) or of the mid-planes (refined cell)
     // and their error bounds; a refined cell's mid-plane lies half a cell
     // before its far plane
@@ -452,7 +473,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     if (!leaf) {
       // ---- refined cell entered through its near face on axis ke: one level
       need64 = w < 2u || ke < 0 || anypar;
-      if (r.x >= v.n_nodes - 7u) { out.flags |= CVX_RAYFLAG_BAD_LINK; break; }
+      if (r.x >= v.n_nodes - 7u) {  // ends the ray at the top of the loop
+        bad = true;
+        continue;
+      }
       uint32_t oct = 0;
       for (int k = 0; k < 3; ++k) {
         const float diff = s_ent - get(S, k);
@@ -469,8 +493,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         I = r.x + oct;
         ++dep;
         w = half;
-        r = ld_rec(rec, I);
-        pay = ld_pay(payp, I);
+        r = ld_rec_t<SMALL>(rec, I);
+        pay = ld_pay_t<SMALL>(payp, I);
         if (STATS) acc.descent++;
         continue;
       }
@@ -490,6 +514,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       const float emin = get(eb, kx);
       uint32_t nsure = 0;
       for (int k = 0; k < 3; ++k) nsure += (get(S, k) - Smin > get(eb, k) + emin) ? 1u : 0u;
+      // exit plane value and bound (the smallest one unless FP64 decides)
+      float Sx = Smin, ex = emin;
       if (nsure != 2u) {
         // FP64 decision from the exact face planes, t = (X - o_k) / d_k with
         // the correctly rounded reciprocal (as the FP64 caster does)
@@ -504,20 +530,22 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
           best = tt < best ? tt : best;
         }
         kx = kb;
+        Sx = get(S, kx);
+        ex = get(eb, kx);
         need64 = true;
         out.flags |= CVX_RAYFLAG_FP64_EXIT;
         if (STATS) acc.fp64_exit++;
       }
-      const float Sx = get(S, kx);
-      const float ex = get(eb, kx);
       if (TRACE) {
         const double t = te_last + ldexp((double)Sx, -(int)db);
         for (int k = 0; k < 3; ++k) out.end[k] = slot.at(k) + t * slot.at(3 + k);
       }
       // length precision guard: rebase once the bound on this segment's
-      // length exceeds 2^-10 of the leaf edge (w base cells)
-      need64 = need64 || (ex + e_ent > 0x1p-10f * (float)w);
-      float len = (Sx - s_ent) * ldexpf(1.0f, (int)dep - (int)db);
+      // length exceeds 2^-10 of the leaf edge (w = 2^(db - dep) base cells);
+      // for a positive float, x > 2^n exactly when its bits exceed those of 2^n
+      const float eseg = ex + e_ent;
+      need64 = need64 || __builtin_bit_cast(uint32_t, eseg) > ((db - dep + 117u) << 23);
+      float len = ldexpf(Sx - s_ent, (int)dep - (int)db);
       len = len > 0.0f ? len : 0.0f;
       // composite; every visited leaf is recorded: for a ray outside the face
       // band the exact segment is positive even when it rounds to 0 here
@@ -558,8 +586,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       }
       if (STATS) acc.outer += !inner;
       I = Nn;
-      r = ld_rec(rec, I);
-      pay = ld_pay(payp, I);
+      r = ld_rec_t<SMALL>(rec, I);
+      pay = ld_pay_t<SMALL>(payp, I);
       set(c, kx, nc);
       s_ent = Sx;
       e_ent = ex;
@@ -931,7 +959,7 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
   if (STATS) acc.leaves += n_rec;
 }
 
-template <int VAR, bool TRACE, bool STATS>
+template <int VAR, bool TRACE, bool STATS, bool SMALL = false>
 __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out) {
   const RaySlot slot{(lds_f64*)(s_ray + threadIdx.x), blockDim.x};
   const V3<double> d = ray_dir(v, px, py);
@@ -946,7 +974,7 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   if (!en.hit) return;
   const V3<bool> up{d.x > 0.0, d.y > 0.0, d.z > 0.0};
   if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
-    cast_fp32<TRACE, STATS>(v, slot, o, d, en, up, sk, acc, out);
+    cast_fp32<TRACE, STATS, SMALL>(v, slot, o, d, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
     cast_fp64<TRACE, STATS>(v, d, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP32_NAIVE) {
@@ -971,7 +999,7 @@ __device__ __forceinline__ DView uniform_view(const DView& v) {
   return u;
 }
 
-template <int VAR, bool TRACE, bool STATS, bool OUT64>
+template <int VAR, bool TRACE, bool STATS, bool OUT64, bool SMALL = false>
 __device__ __forceinline__ void cast_grid(const CastArgs& a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t total = a.hdr->total_work;
@@ -1007,7 +1035,7 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
       const uint32_t x = tx * a.tile_w + lane % a.tile_w, y = ty * a.tile_h + lane / a.tile_w;
       if (x < v.W && y < v.H) {
         Sink sk{nullptr, nullptr, nullptr, 0};
-        cast_ray<VAR, false, STATS>(v, x, y, sk, acc, res);
+        cast_ray<VAR, false, STATS, SMALL>(v, x, y, sk, acc, res);
         const uint64_t pix = v.out_off + (uint64_t)y * v.W + x;
         if constexpr (OUT64) {
           double2* o2 = (double2*)a.out + 2 * pix;
@@ -1031,7 +1059,7 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
             Sink sk{a.leaf_ids + ri * a.max_leaves,
                     a.local_len ? a.local_len + ri * a.max_leaves : nullptr,
                     a.local_len64 ? a.local_len64 + ri * a.max_leaves : nullptr, a.max_leaves};
-            cast_ray<VAR, TRACE, STATS>(v, pix % v.W, pix / v.W, sk, acc, res);
+            cast_ray<VAR, TRACE, STATS, SMALL>(v, pix % v.W, pix / v.W, sk, acc, res);
             a.n_leaves[ri] = res.n;
             a.flags[ri] = res.flags;
             if (a.end_point)
@@ -1074,10 +1102,10 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
 // instances use k_cast).  The FP32 caster fits eight wavefronts per SIMD
 // without spills (its LDS slot, 72 B per lane, then fills 147 KB of a CU's
 // 160 KB).
-template <bool OUT64>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_cast32(
+template <bool OUT64, bool SMALL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CVX_CAST32_WAVES))) void k_cast32(
     CastArgs a) {
-  cast_grid<(int)CVX_VARIANT_FP32_REBASED, false, false, OUT64>(a);
+  cast_grid<(int)CVX_VARIANT_FP32_REBASED, false, false, OUT64, SMALL>(a);
 }
 
 // The FP64 caster keeps its direction, reciprocal and eye in registers (they
@@ -1099,7 +1127,12 @@ int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
     hipLaunchKernelGGL((k_cast64<TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);
   else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && !TRACE && !STATS)
-    hipLaunchKernelGGL((k_cast32<OUT64>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream, a);
+    if (a.small_pools)
+      hipLaunchKernelGGL((k_cast32<OUT64, true>), dim3(wgs), dim3(wg_size), lds,
+                         (hipStream_t)stream, a);
+    else
+      hipLaunchKernelGGL((k_cast32<OUT64, false>), dim3(wgs), dim3(wg_size), lds,
+                         (hipStream_t)stream, a);
   else
     hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);

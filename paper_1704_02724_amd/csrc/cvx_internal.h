@@ -148,6 +148,7 @@ struct CastArgs {
   double* end_point;
   uint64_t* stats;
   uint32_t tile_w, tile_h;
+  uint32_t small_pools;  // every pool the views read has at most 2^28 nodes
 };
 
 // kernel launchers (cvx_upload.hip, cvx_cast.hip); return a hipError_t value
