@@ -411,7 +411,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   uint32_t db = 0, w = 1;
   V3<float> S0{0.f, 0.f, 0.f};
   V3<int32_t> Nk{0, 0, 0};
-  float s_ent = 0.0f, e_ent = 0.0f, beta = 0.0f;
+  float s_ent = 0.0f, e_ent = 0.0f, betac = 0.0f;  // betac = BETA_C beta
   // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
   // current cell I is descended first when it is refined.
   bool bad = false;  // a node index outside the pool (never for a validated pool)
@@ -435,8 +435,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     }
     Nk = V3<int32_t>{0, 0, 0};
     s_ent = 0.0f;
-    beta = ldexpf(tR, (int)db - 50);
+    const float beta = ldexpf(tR, (int)db - 50);
     e_ent = beta;
+    betac = beta * BETA_C;
     if (STATS) acc.rebase++;
   };
   rebase(en.t0);
@@ -450,18 +451,15 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   // exit-axis bit is one bit-field extract, not a chain of selects
   const uint32_t ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
   uint32_t step = 0;
+  uint32_t end_Nn = 0, end_nc = 0, end_dep = 0;  // the move the ray ended on
   for (;; ++step) {
-    if (step >= v.max_steps || bad) {
-      out.flags |= bad ? CVX_RAYFLAG_BAD_LINK : CVX_RAYFLAG_STEP_CAP;
-      break;
-    }
+    if (step >= v.max_steps || bad) break;
     // s-values of the far planes (leaf) or of the mid-planes (refined cell)
     // and their error bounds; a refined cell's mid-plane lies half a cell
     // before its far plane
     const bool leaf = r.x & 1u;
     const uint32_t half = w >> 1;
-    const int32_t off = leaf ? 0 : (int32_t)half;
-    const float betac = beta * BETA_C;
+    const int32_t off = (int32_t)(half & ~(uint32_t)(-(int32_t)(r.x & 1u)));  // 0 for a leaf
     V3<float> S, eb;
     for (int k = 0; k < 3; ++k) {
       const float Nf = (float)(get(Nk, k) - off);
@@ -508,15 +506,21 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     } else {
       // ---- leaf: exit face, certified against the error bounds
       const float Smin = __builtin_fminf(S.x, __builtin_fminf(S.y, S.z));
-      int kx = 2;
-      kx = S.y == Smin ? 1 : kx;
-      kx = S.x == Smin ? 0 : kx;
-      const float emin = get(eb, kx);
-      uint32_t nsure = 0;
-      for (int k = 0; k < 3; ++k) nsure += (get(S, k) - Smin > get(eb, k) + emin) ? 1u : 0u;
+      // exit axis kx (ties to the lower axis), also held one-hot as lane
+      // masks mx, my (z when neither) for the selects below
+      bool mx = S.x == Smin;
+      bool my = !mx & (S.y == Smin);
+      int kx = mx ? 0 : (my ? 1 : 2);
+      const float emin = mx ? eb.x : (my ? eb.y : eb.z);
+      // certified when exactly the two other planes clear the minimum by
+      // more than both bounds (as lane masks: scalar logic, no vector count)
+      const bool s0 = S.x - Smin > eb.x + emin;
+      const bool s1 = S.y - Smin > eb.y + emin;
+      const bool s2 = S.z - Smin > eb.z + emin;
+      const bool cert = (s0 & s1 & !s2) | (s0 & !s1 & s2) | (!s0 & s1 & s2);
       // exit plane value and bound (the smallest one unless FP64 decides)
       float Sx = Smin, ex = emin;
-      if (nsure != 2u) {
+      if (!cert) {
         // FP64 decision from the exact face planes, t = (X - o_k) / d_k with
         // the correctly rounded reciprocal (as the FP64 caster does)
         const double hd = ldexp(1.0, -(int)dep);
@@ -530,6 +534,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
           best = tt < best ? tt : best;
         }
         kx = kb;
+        mx = kb == 0;
+        my = kb == 1;
         Sx = get(S, kx);
         ex = get(eb, kx);
         need64 = true;
@@ -558,10 +564,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       if (TRACE) record(sk, n_rec, I, len);
       ++n_rec;
       // ---- neighbour across the exit face: sibling, next root or G_3 link
-      const uint32_t ck = get(c, kx);
+      const bool mz = !mx & !my;
+      const uint32_t ck = mx ? c.x : (my ? c.y : c.z);
       const uint32_t upk = (ub >> kx) & 1u;
       const uint32_t nc = ck + 2u * upk - 1u;            // wraps to ~0 below 0
-      const bool at_edge = nc >= (v.R << dep);
       const bool root = dep == 0;
       // the sibling lies across the face when the cell is even going up
       // (odd going down); siblings differ in octant bit kx only
@@ -570,25 +576,26 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       if (root) {
         // root array (rare): kept as a branch, not flattened into selects
         asm volatile("");
-        uint32_t rs = rstride[0];
-        rs = kx == 1 ? rstride[1] : rs;
-        rs = kx == 2 ? rstride[2] : rs;
-        sib = upk ? I + rs : I - rs;
+        const uint32_t rs = mx ? rstride[0] : (my ? rstride[1] : rstride[2]);
+        sib = nc >= v.R ? CVX_NONE : (upk ? I + rs : I - rs);
       }
-      uint32_t link = r.y;
-      link = kx == 1 ? r.z : link;
-      link = kx == 2 ? r.w : link;
+      const uint32_t link = mx ? r.y : (my ? r.z : r.w);
       const uint32_t Nn = (root || inner) ? sib : link;
-      // a null link (CVX_NONE) is also >= n_nodes
-      if (at_edge || Nn >= v.n_nodes || (use_stop && 1.0f - T >= v.alpha_stop)) {
-        if (!at_edge && Nn >= v.n_nodes) out.flags |= CVX_RAYFLAG_BAD_LINK;
+      // the canvas boundary has null links (CVX_NONE >= n_nodes) and so would
+      // a broken pool: the two are told apart after the loop
+      if (Nn >= v.n_nodes || (use_stop && 1.0f - T >= v.alpha_stop)) {
+        end_Nn = Nn;
+        end_nc = nc;
+        end_dep = dep;
         break;
       }
       if (STATS) acc.outer += !inner;
       I = Nn;
       r = ld_rec_t<SMALL>(rec, I);
       pay = ld_pay_t<SMALL>(payp, I);
-      set(c, kx, nc);
+      c.x = mx ? nc : c.x;
+      c.y = my ? nc : c.y;
+      c.z = mz ? nc : c.z;
       s_ent = Sx;
       e_ent = ex;
       ke = kx;
@@ -599,10 +606,11 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       const uint32_t m = dL < dep ? dep - dL : 0u;
       const uint32_t mask = (1u << m) - 1u;
       const uint32_t lw = db - dep;  // w = 2^lw
+      const V3<bool> mk{mx, my, mz};
       for (int k = 0; k < 3; ++k) {
         const uint32_t ckk = get(c, k);
         const uint32_t dist = get(up, k) ? (~ckk & mask) : (ckk & mask);
-        set(Nk, k, get(Nk, k) + (int32_t)(((k == kx ? 1u : 0u) + dist) << lw));
+        set(Nk, k, get(Nk, k) + (int32_t)(((get(mk, k) ? 1u : 0u) + dist) << lw));
         set(c, k, ckk >> m);
       }
       w <<= m;
@@ -618,6 +626,12 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       rebase(te);
     }
   }
+  if (bad)
+    out.flags |= CVX_RAYFLAG_BAD_LINK;
+  else if (step >= v.max_steps)
+    out.flags |= CVX_RAYFLAG_STEP_CAP;
+  else if (end_Nn >= v.n_nodes && end_nc < (v.R << end_dep))
+    out.flags |= CVX_RAYFLAG_BAD_LINK;  // a null link inside the canvas
   const float k255 = 1.0f / 255.0f;
   out.rgba[0] = C.x * k255;
   out.rgba[1] = C.y * k255;
