@@ -469,8 +469,12 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     }
     bool need64 = false;
     if (!leaf) {
-      // ---- refined cell entered through its near face on axis ke: one level
-      need64 = w < 2u || ke < 0 || anypar;
+      // ---- refined cell entered through its near face on axis ke: one level.
+      // A refined cell is only reached by a leaf step (ke >= 0), and its
+      // neighbours are of the same depth, so on axis ke the entry value s_ent
+      // and the mid-plane differ by exactly half a cell in N (>= 1 base cell,
+      // far above the bounds): the entry side of that axis needs no test.
+      need64 = w < 2u || anypar;
       if (r.x >= v.n_nodes - 7u) {  // ends the ray at the top of the loop
         bad = true;
         continue;
@@ -478,10 +482,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       uint32_t oct = 0;
       for (int k = 0; k < 3; ++k) {
         const float diff = s_ent - get(S, k);
-        const bool isk = k == ke;
-        const bool far = !isk && diff >= 0.0f;
+        const bool far = diff >= 0.0f;
         const bool sure = __builtin_fabsf(diff) > e_ent + get(eb, k);
-        need64 = need64 || (!isk && !sure);
+        need64 = need64 || !sure;
         const uint32_t b = (get(up, k) == far) ? 1u : 0u;
         oct |= b << k;
         set(Nk, k, get(Nk, k) - (far ? 0 : (int32_t)half));
