@@ -149,7 +149,9 @@ typedef struct {
   uint32_t single_queue; /* 0: the tiles are split into 8 contiguous ranges, one per XCD
                             (workgroup i starts on range i mod 8, then helps the others);
                             1: one queue over all tiles (same result) */
-  uint32_t reserved2;
+  uint32_t per_ray_start; /* 0: when a view's eye lies inside the canvas (off every cell
+                            plane), its rays share the leaf holding the eye, located once
+                            per view; 1: every ray locates its own first leaf (same result) */
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;

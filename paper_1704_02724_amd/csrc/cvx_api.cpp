@@ -19,13 +19,14 @@ using cvx::DView;
 
 struct GraphKey {
   uint32_t variant = ~0u, tw = 0, th = 0, wgs = 0, wg = 0;
-  bool trace = false, stats = false, out64 = false, small = false;
+  bool trace = false, stats = false, out64 = false, small = false, per_ray_start = false;
   const void* out = nullptr;
   const void* stats_ptr = nullptr;
   const void* views = nullptr;
   bool operator==(const GraphKey& o) const {
     return variant == o.variant && tw == o.tw && th == o.th && wgs == o.wgs && wg == o.wg &&
            trace == o.trace && stats == o.stats && out64 == o.out64 && small == o.small &&
+           per_ray_start == o.per_ray_start &&
            out == o.out && stats_ptr == o.stats_ptr && views == o.views;
   }
 };
@@ -313,6 +314,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   if (wgs > (1u << 20)) return fail(ctx, CVX_ERR_INVALID_ARG, "too many workgroups");
   if (o.top_lookup > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "top_lookup must be 0 or 1");
   if (o.single_queue > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "single_queue must be 0 or 1");
+  if (o.per_ray_start > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "per_ray_start must be 0 or 1");
   if (o.out_f64 && o.variant != CVX_VARIANT_FP64_PLAIN)
     return fail(ctx, CVX_ERR_INVALID_ARG, "out_f64 needs the FP64_PLAIN variant");
   const cvx_trace* tr = o.trace;
@@ -394,6 +396,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     const bool top = o.top_lookup == 0 && c.top_depth > 0;
     dv.top_depth = top ? c.top_depth : 0;
     dv.top = top ? c.top : nullptr;
+    dv.start_ok = 0;  // set on the device by k_view_starts
   }
   CastHeader& H = *ctx->h_hdr;
   H.total_work = tr ? (tr->n + 63) / 64 : first;
@@ -431,8 +434,11 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     a.end_point = tr->end_point;
   }
   const bool stats = o.stats != nullptr;
+  const uint32_t shared_start = o.per_ray_start ? 0u : 1u;
   if (!o.use_graph || tr) {
-    int le = cvx::launch_reset(ctx->stream, ctx->d_hdr);
+    int le = cvx::launch_view_starts(ctx->stream, ctx->d_views, ctx->d_hdr, shared_start);
+    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_view_starts");
+    le = cvx::launch_reset(ctx->stream, ctx->d_hdr);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_reset");
     le = cvx::launch_cast(ctx->stream, o.variant, tr != nullptr, stats, o.out_f64 != 0, a, wgs, wg);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_cast");
@@ -448,13 +454,15 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   key.stats = stats;
   key.out64 = o.out_f64 != 0;
   key.small = a.small_pools != 0;
+  key.per_ray_start = o.per_ray_start != 0;
   key.out = out_dev;
   key.stats_ptr = o.stats;
   key.views = ctx->d_views;
   if (!ctx->gexec || !(key == ctx->gkey)) {
     drop_graph(ctx);
     CVX_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    int le = cvx::launch_reset(ctx->stream, ctx->d_hdr);
+    int le = cvx::launch_view_starts(ctx->stream, ctx->d_views, ctx->d_hdr, shared_start);
+    if (le == hipSuccess) le = cvx::launch_reset(ctx->stream, ctx->d_hdr);
     if (le == hipSuccess)
       le = cvx::launch_cast(ctx->stream, o.variant, false, stats, o.out_f64 != 0, a, wgs, wg);
     hipGraph_t g = nullptr;

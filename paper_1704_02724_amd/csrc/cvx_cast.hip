@@ -268,6 +268,24 @@ __device__ __forceinline__ void locate_top(const DView& v, const V3<uint32_t>& C
   c = V3<uint32_t>{C.x >> (D - dep), C.y >> (D - dep), C.z >> (D - dep)};
 }
 
+// First cell of a ray at its FP64 start point q: the view's shared eye leaf
+// when the view has one (every ray then starts at q = eye, off every plane of
+// the deepest grid, so all of them locate the same leaf), else the
+// top-level-table (or root-array) cell above q; a refined cell is descended
+// by the caller.
+__device__ __forceinline__ void start_leaf(const DView& v, const V3<double>& q, const V3<bool>& up,
+                                           uint32_t& I, uint32_t& dep, V3<uint32_t>& c,
+                                           uint4& r) {
+  if (v.start_ok) {
+    I = v.start_node;
+    dep = v.start_dep;
+    c = V3<uint32_t>{v.start_c[0], v.start_c[1], v.start_c[2]};
+    r = ld_rec(v.rec, I);
+  } else {
+    locate_top(v, deep_coords(q, up, v.R, v.max_depth), I, dep, c, r);
+  }
+}
+
 // Root cell containing q (ties go to the side the ray moves into).
 template <class Real>
 __device__ __forceinline__ void root_of(const V3<Real>& q, const V3<bool>& up, uint32_t R,
@@ -404,7 +422,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   uint32_t I, dep = 0;
   V3<uint32_t> c;
   uint4 r;
-  locate_top(v, deep_coords(q, up, v.R, v.max_depth), I, dep, c, r);
+  start_leaf(v, q, up, I, dep, c, r);
   if (STATS) acc.descent += dep;
   uint2 pay = make_uint2(0u, 0u);
 
@@ -668,7 +686,7 @@ __device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, 
   V3<uint32_t> c;
   uint4 r;
   const V3<uint32_t> C0 = deep_coords(q, up, v.R, v.max_depth);
-  locate_top(v, C0, I, dep, c, r);
+  start_leaf(v, q, up, I, dep, c, r);
   bool bad = !descend_int(rec, v.n_nodes, C0, v.max_depth, I, dep, c, r);
   if (STATS) acc.descent += dep;
   double T = 1.0;
@@ -877,7 +895,7 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
   V3<uint32_t> c;
   uint4 r;
   const V3<uint32_t> C0 = deep_coords(q, up, v.R, v.max_depth);
-  locate_top(v, C0, I, dep, c, r);
+  start_leaf(v, q, up, I, dep, c, r);
   bool bad = !descend_int(rec, v.n_nodes, C0, v.max_depth, I, dep, c, r);
   if (STATS) acc.descent += dep;
   V3<Real> p;
@@ -1133,6 +1151,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
   cast_grid<(int)CVX_VARIANT_FP64_PLAIN, TRACE, STATS, OUT64>(a);
 }
 
+// One thread per view: the leaf holding the eye, when every ray of the view
+// starts there (eye strictly inside the canvas and off every plane of the
+// deepest grid: the slab test then gives t0 = 0 and the start point is the
+// eye itself for every direction).
+__global__ void k_view_starts(DView* views, const CastHeader* hdr, uint32_t enable) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hdr->n_views) return;  // the count of this call (a graph replays the launch)
+  DView& v = views[i];
+  v.start_ok = 0u;
+  if (!enable) return;
+  const double Rd = (double)v.R;
+  bool ok = true;
+  for (int k = 0; k < 3; ++k) {
+    const double Q = ldexp(v.o[k], (int)v.max_depth);
+    ok = ok && v.o[k] > 0.0 && v.o[k] < Rd && floor(Q) != Q;
+  }
+  if (!ok) return;
+  const V3<double> q{v.o[0], v.o[1], v.o[2]};
+  const V3<bool> up{true, true, true};  // no plane ties: the direction plays no part
+  const V3<uint32_t> C = deep_coords(q, up, v.R, v.max_depth);
+  uint32_t I, dep;
+  V3<uint32_t> c;
+  uint4 r;
+  locate_top(v, C, I, dep, c, r);
+  if (!descend_int(v.rec, v.n_nodes, C, v.max_depth, I, dep, c, r)) return;
+  v.start_node = I;
+  v.start_dep = dep;
+  v.start_c[0] = c.x;
+  v.start_c[1] = c.y;
+  v.start_c[2] = c.z;
+  v.start_ok = 1u;
+}
+
 __global__ void k_reset(CastHeader* hdr) {
   if (blockIdx.x == 0 && threadIdx.x < CVX_NQ) hdr->queue[threadIdx.x].next = 0u;
 }
@@ -1190,6 +1241,12 @@ int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out
     default:
       return (int)hipErrorInvalidValue;
   }
+}
+
+int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable) {
+  hipLaunchKernelGGL(k_view_starts, dim3((CVX_MAX_VIEWS + 63u) / 64u), dim3(64), 0,
+                     (hipStream_t)stream, views, hdr, enable);
+  return (int)hipGetLastError();
 }
 
 int launch_reset(void* stream, CastHeader* hdr) {

@@ -107,6 +107,11 @@ struct DView {
   uint32_t n_nodes;     // node ids at or above this are never loaded
   uint32_t top_depth;   // 0: ray starts descend from the root array
   const uint32_t* top;  // (R 2^top_depth)^3 node ids, x fastest
+  // the leaf holding the eye when every ray of the view starts there (eye
+  // inside the canvas, off every plane of the deepest grid), written on the
+  // device before the cast; start_ok = 0: each ray locates its first leaf
+  uint32_t start_ok, start_node, start_dep;
+  uint32_t start_c[3];  // its integer coordinates at start_dep
 };
 
 // Work queues: the work items (tiles or 64-ray chunks) are split into
@@ -171,6 +176,8 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
 int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out_f64,
                 const CastArgs& a, uint32_t workgroups, uint32_t wg_size);
 int launch_reset(void* stream, CastHeader* hdr);
+// the shared first leaf of every view whose eye lies inside its canvas
+int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable);
 // one level of a stroke's walk (cvx_stroke.hip); items == nullptr: the roots
 int launch_stroke_visit(void* stream, const StrokeItem* items, uint32_t n, const StrokeArgs& a,
                         const void* stamps, const void* rec, void* pay, uint64_t n_nodes,

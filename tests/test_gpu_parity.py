@@ -165,6 +165,40 @@ def test_top_table_matches_root_descent(sess, R, depth, seed):
         np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("R,depth,seed", [(1, 9, 64), (2, 7, 65), (3, 6, 66)])
+def test_shared_eye_leaf_matches_per_ray_start(sess, R, depth, seed):
+    """Views whose eye lies inside the canvas share the eye's leaf as the first
+    leaf of every ray; the images equal those of per-ray starts, also for eyes
+    on a cell plane (no sharing), on the canvas boundary and outside, and in
+    a graph replayed with fewer views."""
+    cv = trees.random_tree(R, depth, seed=seed, max_nodes=40000, leaf_format=LEAF_RGBA8_F16)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    views = _views_around(rng, 3, 40, 24, inside=True, R=R)
+    off = 3 * 40 * 24
+    tgt = np.array([0.5, 0.5, 0.5]) * R
+    for e in ([0.5 * R, 0.3 * R, 0.7 * R],            # on a plane of every depth
+              [0.0, 0.41 * R, 0.37 * R],              # on the canvas boundary
+              [-0.3 * R, 1.2 * R, 0.4 * R]):          # outside
+        e = np.array(e)
+        views.append(make_view(e, tgt - e, 0.8, 40, 24, out_offset_px=off))
+        off += 40 * 24
+    sess.upload(0, cv)
+    for var in ("fp32_rebased", "fp64_plain", "fp32_cell_local"):
+        a = sess.render(views, var, per_ray_start=0).cpu().numpy()
+        b = sess.render(views, var, per_ray_start=1).cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+    torch = sess.torch
+    out = torch.full((off, 4), -1.0, dtype=torch.float32, device=sess.device)
+    sess.render(views, "fp32_rebased", out=out, use_graph=True)
+    full = out.cpu().numpy()
+    out.fill_(-1.0)
+    sess.render(views[:2], "fp32_rebased", out=out, use_graph=True)   # same graph, 2 views
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got[:2 * 40 * 24], full[:2 * 40 * 24])
+    assert np.all(got[2 * 40 * 24:] == -1.0)
+
+
 def test_graph_replay_matches_eager(sess):
     torch = sess.torch
     w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=64, H=48)
