@@ -111,8 +111,10 @@ struct Entry {
   bool hit;
 };
 
-// Slab test of the ray against the canvas box [0, R]^3 (FP64).
-__device__ __forceinline__ Entry canvas_entry(const V3<double>& o, const V3<double>& d, double Rd) {
+// Slab test of the ray against the canvas box [0, R]^3 (FP64), with the
+// correctly rounded reciprocal direction inv (one division per axis per ray).
+__device__ __forceinline__ Entry canvas_entry(const V3<double>& o, const V3<double>& d,
+                                              const V3<double>& inv, double Rd) {
   Entry e;
   double tin = -__builtin_inf(), tout = __builtin_inf();
   int kin = -1, side = 0;
@@ -120,7 +122,8 @@ __device__ __forceinline__ Entry canvas_entry(const V3<double>& o, const V3<doub
   for (int k = 0; k < 3; ++k) {
     const double dk = get(d, k), ok = get(o, k);
     if (dk != 0.0) {
-      double ta = (0.0 - ok) / dk, tb = (Rd - ok) / dk;
+      const double ik = get(inv, k);
+      double ta = (0.0 - ok) * ik, tb = (Rd - ok) * ik;
       double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
       if (lo > tin) {
         tin = lo;
@@ -385,10 +388,11 @@ typedef __attribute__((address_space(3))) double lds_f64;
 struct RaySlot {
   lds_f64* p;  // this lane's first component
   uint32_t stride;
-  __device__ __forceinline__ void put(const V3<double>& o, const V3<double>& d) const {
+  __device__ __forceinline__ void put(const V3<double>& o, const V3<double>& d,
+                                      const V3<double>& inv) const {
     p[0] = o.x; p[stride] = o.y; p[2 * stride] = o.z;
     p[3 * stride] = d.x; p[4 * stride] = d.y; p[5 * stride] = d.z;
-    p[6 * stride] = 1.0 / d.x; p[7 * stride] = 1.0 / d.y; p[8 * stride] = 1.0 / d.z;
+    p[6 * stride] = inv.x; p[7 * stride] = inv.y; p[8 * stride] = inv.z;
   }
   // component j (0-2 eye, 3-5 direction, 6-8 reciprocal direction), read
   // through an opaque pointer so the load stays on the rare path that needs it
@@ -397,12 +401,12 @@ struct RaySlot {
 
 template <bool TRACE, bool STATS, bool SMALL>
 __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& o,
-                          const V3<double>& d, const Entry& en, const V3<bool>& up, Sink sk,
-                          Acc& acc, Out& out) {
+                          const V3<double>& d, const V3<double>& inv, const Entry& en,
+                          const V3<bool>& up, Sink sk, Acc& acc, Out& out) {
   const double Rd = (double)v.R;
   const void* rec = v.rec;
   const void* payp = v.pay;
-  slot.put(o, d);
+  slot.put(o, d, inv);
   V3<float> tD;
   for (int k = 0; k < 3; ++k) {
     const double dk = get(d, k);
@@ -668,14 +672,12 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
 // ((integer + side) 2^-dep - o_k) / d_k every step, FP64 compositing.
 // ----------------------------------------------------------------------------
 template <bool TRACE, bool STATS>
-__device__ void cast_fp64(const DView& v, const V3<double>& d, const Entry& en, const V3<bool>& up,
-                          Sink sk, Acc& acc, Out& out) {
+__device__ void cast_fp64(const DView& v, const V3<double>& d, const V3<double>& inv,
+                          const Entry& en, const V3<bool>& up, Sink sk, Acc& acc, Out& out) {
   const V3<double> o{v.o[0], v.o[1], v.o[2]};
   const double Rd = (double)v.R;
   const void* rec = v.rec;
   const bool use_stop = v.alpha_stop < 1.0f;
-  V3<double> inv;
-  for (int k = 0; k < 3; ++k) set(inv, k, 1.0 / get(d, k));
   V3<double> q;
   for (int k = 0; k < 3; ++k) {
     double qk = get(o, k) + en.t0 * get(d, k);
@@ -1005,13 +1007,14 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   out.steps = 0;
   out.end[0] = out.end[1] = out.end[2] = 0.0;
   if (STATS) acc.rays++;
-  const Entry en = canvas_entry(o, d, (double)v.R);
+  const V3<double> inv{1.0 / d.x, 1.0 / d.y, 1.0 / d.z};
+  const Entry en = canvas_entry(o, d, inv, (double)v.R);
   if (!en.hit) return;
   const V3<bool> up{d.x > 0.0, d.y > 0.0, d.z > 0.0};
   if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
-    cast_fp32<TRACE, STATS, SMALL>(v, slot, o, d, en, up, sk, acc, out);
+    cast_fp32<TRACE, STATS, SMALL>(v, slot, o, d, inv, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
-    cast_fp64<TRACE, STATS>(v, d, en, up, sk, acc, out);
+    cast_fp64<TRACE, STATS>(v, d, inv, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP32_NAIVE) {
     cast_naive<TRACE, STATS>(v, d, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP32_CELL_LOCAL) {
