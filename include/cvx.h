@@ -302,7 +302,8 @@ typedef struct {
  * n_stamps (1..CVX_MAX_STAMPS) x 4 doubles, each r finite and >= 0, read
  * during the call.  A stroke still in progress on the canvas is completed
  * first.  *pending receives the number of leaves waiting for a split.
- * Synchronous; on an argument error nothing changes. */
+ * Synchronous; on an argument error nothing changes (a device error during
+ * the walk can leave the stroke painted into part of the leaves). */
 int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, const double* stamps,
                      uint32_t n_stamps, uint64_t* pending);
 
@@ -311,8 +312,10 @@ int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, cons
  * leaf's payload from before the stroke), the stroke is painted into the
  * children, and *pending receives the number of children that still need a
  * split.  With no stroke in progress it returns CVX_OK and *pending = 0.
- * Synchronous; on an error (e.g. CVX_ERR_OOM while the pool grows) the pool is
- * left as after the previous step and the stroke is dropped. */
+ * Synchronous.  On an error the stroke is dropped: if the splits fail (e.g.
+ * CVX_ERR_OOM while the pool grows) the pool is left as after the previous
+ * step; a device error after them leaves the splits in place, their children
+ * possibly not yet painted. */
 int cvx_stroke_step(cvx_ctx* ctx, int canvas_id, uint64_t* pending);
 
 /* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
