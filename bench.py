@@ -251,8 +251,9 @@ def main():
                          "(also the reference for hardware byte counters); 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the ray caster has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the ray caster renders "
+              "on one GPU; rays are independent, so more GPUs would split the tiles of a "
+              "replicated pool", file=sys.stderr)
         sys.exit(2)
 
     import torch
