@@ -45,23 +45,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(variant, workload):
-    """HBM bytes per launch from the committed rocprofv3 summary of this kernel
-    and workload, or None when the kernel source changed since it was taken."""
+def profiled_counts(variant, workload):
+    """(HBM bytes, VALU wave-instructions) per launch from the committed
+    rocprofv3 summary of this kernel and workload; (None, None) when the kernel
+    source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"k_cast_{variant}_{workload}.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     vals = {}
     for line in open(path):
-        if ":" in line:
+        if line.startswith("| SQ_INSTS_VALU |"):
+            vals["valu"] = line.split("|")[2].strip()
+        elif ":" in line:
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return None, None
+    out = []
+    for k in ("traffic_bytes_per_launch", "valu"):
+        try:
+            out.append(float(vals[k]))
+        except (KeyError, ValueError):
+            out.append(None)
+    return tuple(out)
 
 
 def build_workload(name, threads):
@@ -329,7 +335,7 @@ def main():
     alg_bytes = 16.0 * s[0] + 8.0 * s[1] + 4.0 * (s[2] + s[3])
     kernel_s = per.mean() * 1e-3
     achieved = alg_bytes / kernel_s
-    traffic_b = profiled_traffic(args.variant, args.workload)
+    traffic_b, valu_instr = profiled_counts(args.variant, args.workload)
 
     # --- FP64 plain baseline on the same GPU
     fp64 = None
@@ -436,6 +442,11 @@ def main():
             "kernel_ms_median": round(float(np.median(per)), 4),
             "measured_copy_GBps": round(copy_bps / 1e9, 1) if copy_bps else None,
             "frac_of_measured_copy": round(achieved / copy_bps, 4) if copy_bps else None,
+            # vector issue, the measured limit: wave64 VALU instructions per
+            # launch (profile) per SIMD-cycle at 2.4 GHz over 1024 SIMDs
+            "valu_wave_instr_per_launch": valu_instr,
+            "valu_per_simd_cycle": (round(valu_instr / (kernel_s * 1024 * 2.4e9), 3)
+                                    if valu_instr else None),
         },
         "fp64_plain_mrays": round(fp64, 2) if fp64 else None,
         "speedup_vs_fp64_plain": round(value / fp64, 3) if fp64 else None,
