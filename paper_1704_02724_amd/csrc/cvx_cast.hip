@@ -416,7 +416,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   const float tR = (float)(en.t1 + Rd + 1.0);
   const bool use_stop = v.alpha_stop < 1.0f;
 
-  // first leaf: FP64 point location from the root
+  // first leaf: the view's shared eye leaf, else FP64 point location from the
+  // top-level table or the root array (descended to the leaf by the rebase)
   V3<double> q;
   for (int k = 0; k < 3; ++k) {
     double qk = get(o, k) + en.t0 * get(d, k);
