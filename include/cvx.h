@@ -288,12 +288,19 @@ int cvx_read_payloads(cvx_ctx* ctx, int canvas_id, uint64_t first, uint64_t coun
  * are deferred: cvx_stroke_begin paints the stroke into the leaves that exist
  * and records the leaves that still need a split; each cvx_stroke_step splits
  * them by one level and paints the new children.  When *pending reaches 0 the
- * canvas is the one the stroke would give applied at once. */
+ * canvas is the one the stroke would give applied at once (then, with
+ * coarsen = 1, coarsened as stated below: *pending also counts the cells
+ * waiting for a merge). */
 typedef struct {
   double rgb[3];   /* brush colour, each in [0, 1] */
   double sigma;    /* opacity density per brush radius, finite, >= 0 */
   double radius;   /* brush radius in world units, finite, > 0 */
   double k_refine; /* leaves are split while their edge exceeds radius / k_refine; > 0 */
+  uint32_t coarsen; /* 1: after the splits, coarsen without loss, one level per step: a
+                       refined cell the stamps overlap whose 8 children are leaves with
+                       identical payloads becomes one leaf of twice the optical depth
+                       per edge, until none is left; 0: no coarsening */
+  uint32_t reserved;
 } cvx_stroke;
 
 #define CVX_MAX_STAMPS 65536u
@@ -311,7 +318,9 @@ int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, cons
  * (through the same machinery as cvx_edit_pool, with children that take the
  * leaf's payload from before the stroke), the stroke is painted into the
  * children, and *pending receives the number of children that still need a
- * split.  With no stroke in progress it returns CVX_OK and *pending = 0.
+ * split; once none is left, a coarsening stroke merges every waiting cell
+ * instead (cvx_edit_pool COARSEN) and *pending receives the number of cells
+ * that can merge next.  With no stroke in progress it returns CVX_OK and *pending = 0.
  * Synchronous.  On an error the stroke is dropped: if the splits fail (e.g.
  * CVX_ERR_OOM while the pool grows) the pool is left as after the previous
  * step; a device error after them leaves the splits in place, their children

@@ -5,6 +5,11 @@ TEST INFRASTRUCTURE ONLY: imported by the test-suite and the benchmark, never
 by the library.  Plain Python in FP64, one leaf at a time; it shares no code
 with the GPU path (nor with the canvas builder, against which it is pinned).
 
+Optionally (`merge_uniform`) the cells the stroke left uniform are coarsened
+back, without loss: a refined cell the stamps overlap whose 8 children are
+leaves with identical payloads becomes one leaf of twice the optical depth
+per edge, until no such cell remains.
+
 A canvas is taken in canonical form: a dict mapping every leaf's cell
 (depth, x, y, z) -- integer coordinates at that depth, the R^3 root array at
 depth 0 -- to its payload tuple ((r, g, b, kappa) doubles for the F64 leaf
@@ -162,6 +167,56 @@ def apply_stroke(leaves, fmt, R, max_depth, root_edge, origin, stamps, rgb, sigm
     for cell, pay in leaves.items():
         visit(cell, pay)
     return out, split
+
+
+def parent_payload(child, fmt):
+    """The leaf that replaces 8 identical children: same colour, twice the
+    optical depth per edge (None when that overflows the half format)."""
+    if fmt == F64:
+        return (child[0], child[1], child[2], child[3] * 2.0)
+    kap = _f16_value(child[4]) * 2.0
+    if kap > 65504.0:
+        return None
+    a = int(np.rint(255.0 * (1.0 - math.exp(-kap))))
+    return (child[0], child[1], child[2], a, _f16_bits(kap), 0)
+
+
+def merge_uniform(leaves, fmt, root_edge, origin, stamps):
+    """Sec. 5.2-5.3 coarsening, read as lossless: every refined cell that the
+    stamps overlap and whose 8 children are leaves with identical payloads
+    becomes one leaf (same colour, twice the optical depth per edge), repeated
+    until no such cell is left.  Returns (new canonical dict, merged cells)."""
+    stamps = [tuple(float(v) for v in s) for s in np.asarray(stamps, np.float64)]
+    box = _stroke_box(stamps)
+    out = dict(leaves)
+    merged = set()
+    while True:
+        groups = {}
+        for (d, x, y, z) in out:
+            if d > 0:
+                groups.setdefault((d - 1, x >> 1, y >> 1, z >> 1), []).append((d, x, y, z))
+        done = []
+        for parent, kids in groups.items():
+            if len(kids) != 8:
+                continue
+            pays = {out[c] for c in kids}
+            if len(pays) != 1:
+                continue
+            d, x, y, z = parent
+            e = math.ldexp(root_edge, -d)
+            lo = (origin[0] + x * e, origin[1] + y * e, origin[2] + z * e)
+            if _outside(lo, e, box) or not any(_box_dist2(lo, e, s) < s[3] * s[3] for s in stamps):
+                continue
+            pp = parent_payload(next(iter(pays)), fmt)
+            if pp is not None:
+                done.append((parent, kids, pp))
+        if not done:
+            return out, merged
+        for parent, kids, pp in done:
+            for c in kids:
+                del out[c]
+            out[parent] = pp
+            merged.add(parent)
 
 
 def immediate(leaves, fmt, R, max_depth, root_edge, origin, stamps, rgb, sigma, radius, k):

@@ -959,7 +959,8 @@ void child_payload(const uint8_t* parent, uint32_t fmt, uint8_t* child) {
 // One walk of the stroke from a frontier (nullptr: the root array) down to
 // the leaves, level by level on the GPU; the leaves still waiting for a split
 // are appended to c.stroke.pending with their payloads from before the stroke.
-int stroke_walk(cvx_ctx* ctx, DevCanvas& c, const std::vector<cvx::StrokeItem>* start) {
+int stroke_walk(cvx_ctx* ctx, DevCanvas& c, const std::vector<cvx::StrokeItem>* start,
+                uint32_t merge = 0) {
   cvx::StrokeState& st = c.stroke;
   const uint32_t lb = leaf_bytes(c.desc.leaf_format);
   const uint32_t R = c.desc.R;
@@ -994,7 +995,8 @@ int stroke_walk(cvx_ctx* ctx, DevCanvas& c, const std::vector<cvx::StrokeItem>* 
     int le = cvx::launch_stroke_visit(ctx->stream, (const cvx::StrokeItem*)b_cur.p, (uint32_t)n,
                                       st.args, b_stamps.p, c.rec, c.pay, c.n_nodes,
                                       (cvx::StrokeItem*)b_next.p, cnt, (uint32_t)(8 * n),
-                                      (cvx::StrokeItem*)b_pend.p, b_ppay.p, cnt + 1, (uint32_t)n);
+                                      (cvx::StrokeItem*)b_pend.p, b_ppay.p, cnt + 1, (uint32_t)n,
+                                      merge);
     if (le != hipSuccess) { e = (hipError_t)le; where = "k_stroke_visit"; break; }
     uint32_t h[2] = {0, 0};
     STEP(hipMemcpyAsync(h, b_count.p, 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -1018,12 +1020,85 @@ int stroke_walk(cvx_ctx* ctx, DevCanvas& c, const std::vector<cvx::StrokeItem>* 
   return CVX_OK;
 }
 
+// Payload of the leaf that replaces 8 identical children: same colour, twice
+// the optical depth per edge (A recomputed).  False when the half kappa
+// would overflow.
+bool parent_payload(const uint8_t* child, uint32_t fmt, uint8_t* parent) {
+  if (fmt == CVX_LEAF_F64) {
+    double q[4];
+    std::memcpy(q, child, 32);
+    q[3] = q[3] * 2.0;
+    std::memcpy(parent, q, 32);
+    return std::isfinite(q[3]);
+  }
+  uint16_t h;
+  std::memcpy(&h, child + 4, 2);
+  const double kp = (double)half_to_float(h) * 2.0;
+  if (kp > 65504.0) return false;
+  const uint16_t hp = float_to_half((float)kp);
+  std::memcpy(parent, child, 8);
+  parent[3] = (uint8_t)std::lrint(255.0 * (1.0 - std::exp(-kp)));
+  std::memcpy(parent + 4, &hp, 2);
+  parent[6] = parent[7] = 0;
+  return true;
+}
+
+// When a coarsening stroke has no split left, the next steps merge: the
+// walk lists the cells that can merge now.
+int stroke_enter_merge(cvx_ctx* ctx, DevCanvas& c) {
+  cvx::StrokeState& st = c.stroke;
+  if (!st.pending.empty() || !st.coarsen || st.merging) return CVX_OK;
+  st.merging = true;
+  return stroke_walk(ctx, c, nullptr, 1);
+}
+
+// One level of merges: COARSEN edits for the listed cells, then the walk for
+// the next level.
+int stroke_merge_step(cvx_ctx* ctx, DevCanvas& c) {
+  cvx::StrokeState& st = c.stroke;
+  const uint32_t fmt = c.desc.leaf_format, lb = leaf_bytes(fmt);
+  std::vector<uint32_t> nodes;
+  std::vector<uint8_t> pays;
+  for (size_t i = 0; i < st.pending.size(); ++i) {
+    uint8_t pp[32];
+    if (!parent_payload(st.pending_pay.data() + i * lb, fmt, pp)) continue;
+    nodes.push_back(st.pending[i].node);
+    pays.insert(pays.end(), pp, pp + lb);
+  }
+  std::vector<uint32_t> ord(nodes.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (uint32_t)i;
+  std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return nodes[a] < nodes[b]; });
+  std::vector<cvx_edit> edits(nodes.size());
+  for (size_t i = 0; i < ord.size(); ++i) {
+    edits[i].op = CVX_EDIT_COARSEN;
+    edits[i].node = nodes[ord[i]];
+    edits[i].first_payload = ord[i];
+  }
+  st.pending.clear();
+  st.pending_pay.clear();
+  if (!edits.empty()) {
+    int rc = edit_impl(ctx, c, edits.data(), (uint32_t)edits.size(), pays.data(),
+                       (uint64_t)nodes.size(), nullptr);
+    if (rc != CVX_OK) return rc;
+    // a merge that overflowed the half kappa stays refined; only merged cells
+    // can make their parents mergeable, so walk again only after merges
+    return stroke_walk(ctx, c, nullptr, 1);
+  }
+  return CVX_OK;
+}
+
 int stroke_step_impl(cvx_ctx* ctx, DevCanvas& c, uint64_t* pending) {
   cvx::StrokeState& st = c.stroke;
   if (!st.active || st.pending.empty()) {
     st = cvx::StrokeState();
     if (pending) *pending = 0;
     return CVX_OK;
+  }
+  if (st.merging) {
+    int rc = stroke_merge_step(ctx, c);
+    if (rc != CVX_OK || st.pending.empty()) st = cvx::StrokeState();
+    if (pending) *pending = st.pending.size();
+    return rc;
   }
   const uint32_t fmt = c.desc.leaf_format, lb = leaf_bytes(fmt);
   const size_t n = st.pending.size();
@@ -1070,6 +1145,7 @@ int stroke_step_impl(cvx_ctx* ctx, DevCanvas& c, uint64_t* pending) {
   st.pending.clear();
   st.pending_pay.clear();
   rc = stroke_walk(ctx, c, &kids);
+  if (rc == CVX_OK) rc = stroke_enter_merge(ctx, c);
   if (rc != CVX_OK) {
     st = cvx::StrokeState();
     return rc;
@@ -1101,13 +1177,15 @@ int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, cons
     return fail(ctx, CVX_ERR_INVALID_ARG, "stroke radius must be finite and > 0");
   if (!(std::isfinite(stroke->k_refine) && stroke->k_refine > 0.0))
     return fail(ctx, CVX_ERR_INVALID_ARG, "stroke k_refine must be finite and > 0");
+  if (stroke->coarsen > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "stroke coarsen must be 0 or 1");
   for (uint64_t j = 0; j < 4ull * n_stamps; ++j)
     if (!std::isfinite(stamps[j]) || (j % 4 == 3 && stamps[j] < 0.0))
       return fail(ctx, CVX_ERR_INVALID_ARG,
                   "stamp " + std::to_string(j / 4) + " not finite or with r < 0");
   CVX_HIP(hipSetDevice(ctx->device));
-  // a stroke still in progress is completed first (at most one level per step)
-  for (uint32_t guard = 0; c.stroke.active && guard <= 64; ++guard) {
+  // a stroke still in progress is completed first (one level per step: at
+  // most max_depth levels of splits and as many of merges)
+  for (uint32_t guard = 0; c.stroke.active && guard <= 2 * CVX_MAX_DEPTH + 2; ++guard) {
     int rc = stroke_step_impl(ctx, c, nullptr);
     if (rc != CVX_OK) return rc;
   }
@@ -1127,8 +1205,10 @@ int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, cons
   st.args.n_stamps = n_stamps;
   st.stamps.assign(stamps, stamps + 4ull * n_stamps);
   st.active = true;
+  st.coarsen = stroke->coarsen != 0;
   c.stroke = std::move(st);
   int rc = stroke_walk(ctx, c, nullptr);
+  if (rc == CVX_OK) rc = stroke_enter_merge(ctx, c);
   if (rc != CVX_OK) {
     c.stroke = cvx::StrokeState();
     return rc;

@@ -52,6 +52,8 @@ struct StrokeArgs {
 // payloads from before the stroke.
 struct StrokeState {
   bool active = false;
+  bool coarsen = false;  // merge uniform cells once the splits are done
+  bool merging = false;  // pending holds cells to merge, not leaves to split
   StrokeArgs args{};
   std::vector<double> stamps;  // 4 per stamp: x, y, z, r
   std::vector<StrokeItem> pending;
@@ -178,10 +180,12 @@ int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out
 int launch_reset(void* stream, CastHeader* hdr);
 // the shared first leaf of every view whose eye lies inside its canvas
 int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable);
-// one level of a stroke's walk (cvx_stroke.hip); items == nullptr: the roots
+// one level of a stroke's walk (cvx_stroke.hip); items == nullptr: the roots;
+// merge = 1: find cells to merge instead of painting and splitting
 int launch_stroke_visit(void* stream, const StrokeItem* items, uint32_t n, const StrokeArgs& a,
                         const void* stamps, const void* rec, void* pay, uint64_t n_nodes,
                         StrokeItem* next, uint32_t* next_count, uint32_t next_cap,
-                        StrokeItem* pend, void* pend_pay, uint32_t* pend_count, uint32_t pend_cap);
+                        StrokeItem* pend, void* pend_pay, uint32_t* pend_count, uint32_t pend_cap,
+                        uint32_t merge);
 
 }  // namespace cvx

@@ -15,7 +15,10 @@
 // their 8 children to the next frontier; a leaf that still needs a split is
 // appended to the pending list with its payload as it was before the stroke
 // (its children must inherit that, not the immediate paint); a leaf whose
-// centre lies in a stamp is painted in place.  Box and centre tests and the
+// centre lies in a stamp is painted in place.  In merge mode (a coarsening
+// stroke, once its splits are done) the walk lists the refined cells the
+// stamps overlap whose 8 children are leaves with identical payload bytes,
+// and paints nothing.  Box and centre tests and the
 // mix are FP64 with the operations in the order of their definition
 // (no contraction), so the result does not depend on the launch.
 #include <hip/hip_runtime.h>
@@ -85,7 +88,8 @@ __global__ void k_stroke_visit(const StrokeItem* __restrict__ items, uint32_t n,
                                void* pay, uint64_t n_nodes, StrokeItem* __restrict__ next,
                                uint32_t* __restrict__ next_count, uint32_t next_cap,
                                StrokeItem* __restrict__ pend, void* __restrict__ pend_pay,
-                               uint32_t* __restrict__ pend_count, uint32_t pend_cap) {
+                               uint32_t* __restrict__ pend_count, uint32_t pend_cap,
+                               uint32_t merge) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   StrokeItem it;
@@ -111,6 +115,44 @@ __global__ void k_stroke_visit(const StrokeItem* __restrict__ items, uint32_t n,
   }
   if (!overlap) return;
   const uint32_t x = rec[it.node].x;
+  if (merge) {
+    // a refined cell whose 8 children are leaves with identical payloads is
+    // listed (with its first child's payload); otherwise its children are
+    // looked at on the next level
+    if ((x & 1u) || (uint64_t)x + 8 > n_nodes) return;
+    bool uni = true;
+    for (uint32_t o = 0; o < 8; ++o) uni = uni && (rec[x + o].x & 1u);
+    if (uni) {
+      if (a.fmt == CVX_LEAF_F64) {
+        const double* p0 = (const double*)pay + 4 * (uint64_t)x;
+        for (uint32_t o = 1; o < 8 && uni; ++o) {
+          const double* po = p0 + 4 * o;
+          for (int k = 0; k < 4; ++k)
+            uni = uni && __builtin_bit_cast(uint64_t, po[k]) == __builtin_bit_cast(uint64_t, p0[k]);
+        }
+      } else {
+        const uint2 p0 = ((const uint2*)pay)[x];
+        for (uint32_t o = 1; o < 8; ++o) {
+          const uint2 po = ((const uint2*)pay)[x + o];
+          uni = uni && po.x == p0.x && po.y == p0.y;
+        }
+      }
+    }
+    if (uni) {
+      const uint32_t slot = atomicAdd(pend_count, 1u);
+      if (slot < pend_cap) {
+        pend[slot] = it;
+        if (a.fmt == CVX_LEAF_F64) {
+          const double* p0 = (const double*)pay + 4 * (uint64_t)x;
+          double* q = (double*)pend_pay + 4 * (uint64_t)slot;
+          for (int k = 0; k < 4; ++k) q[k] = p0[k];
+        } else {
+          ((uint2*)pend_pay)[slot] = ((const uint2*)pay)[x];
+        }
+      }
+      return;
+    }
+  }
   if (!(x & 1u)) {
     if ((uint64_t)x + 8 > n_nodes) return;
     const uint32_t slot = atomicAdd(next_count, 8u);
@@ -126,6 +168,7 @@ __global__ void k_stroke_visit(const StrokeItem* __restrict__ items, uint32_t n,
     }
     return;
   }
+  if (merge) return;  // a leaf: nothing to merge below it
   if (e > a.hmin && it.depth < a.max_depth) {
     const uint32_t slot = atomicAdd(pend_count, 1u);
     if (slot < pend_cap) {
@@ -147,12 +190,13 @@ __global__ void k_stroke_visit(const StrokeItem* __restrict__ items, uint32_t n,
 int launch_stroke_visit(void* stream, const StrokeItem* items, uint32_t n, const StrokeArgs& a,
                         const void* stamps, const void* rec, void* pay, uint64_t n_nodes,
                         StrokeItem* next, uint32_t* next_count, uint32_t next_cap,
-                        StrokeItem* pend, void* pend_pay, uint32_t* pend_count, uint32_t pend_cap) {
+                        StrokeItem* pend, void* pend_pay, uint32_t* pend_count, uint32_t pend_cap,
+                        uint32_t merge) {
   if (!n) return hipSuccess;
   const uint32_t bs = 256;
   hipLaunchKernelGGL(k_stroke_visit, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream,
                      items, n, a, (const double4*)stamps, (const uint4*)rec, pay, n_nodes, next,
-                     next_count, next_cap, pend, pend_pay, pend_count, pend_cap);
+                     next_count, next_cap, pend, pend_pay, pend_count, pend_cap, merge);
   return (int)hipGetLastError();
 }
 

@@ -58,7 +58,8 @@ CVX_MAX_STAMPS = 65536
 
 class cvx_stroke(ctypes.Structure):
     _fields_ = [("rgb", ctypes.c_double * 3), ("sigma", ctypes.c_double),
-                ("radius", ctypes.c_double), ("k_refine", ctypes.c_double)]
+                ("radius", ctypes.c_double), ("k_refine", ctypes.c_double),
+                ("coarsen", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class cvx_canvas_desc(ctypes.Structure):
@@ -275,12 +276,14 @@ def cvx_read_payloads(ctx, canvas_id, dtype, first=0, count=None):
     return out
 
 
-def cvx_stroke_begin(ctx, canvas_id, stamps, rgb, sigma, radius, k_refine) -> int:
+def cvx_stroke_begin(ctx, canvas_id, stamps, rgb, sigma, radius, k_refine, coarsen=False) -> int:
     """Start a brush stroke (stamps: (n, 4) x, y, z, r in world units); returns
-    the number of leaves waiting for a split."""
+    the number of leaves waiting for a split (or, for a coarsening stroke with
+    no split to make, of cells waiting for a merge)."""
     st = cvx_stroke()
     st.rgb[:] = [float(v) for v in rgb]
     st.sigma, st.radius, st.k_refine = float(sigma), float(radius), float(k_refine)
+    st.coarsen = 1 if coarsen else 0
     arr = np.ascontiguousarray(stamps, np.float64).reshape(-1, 4)
     pend = ctypes.c_uint64()
     _check(ctx, _lib.cvx_stroke_begin(ctx, int(canvas_id), ctypes.byref(st),

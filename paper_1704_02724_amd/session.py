@@ -49,11 +49,12 @@ class Session:
         self.torch.cuda.current_stream(self.device).synchronize()
         return cvx.cvx_edit_pool(self.ctx, canvas_id, edits, payloads)
 
-    def stroke_begin(self, canvas_id, stamps, rgb, sigma, radius, k_refine):
+    def stroke_begin(self, canvas_id, stamps, rgb, sigma, radius, k_refine, coarsen=False):
         """Paint a brush stroke into the existing leaves (cvx_stroke_begin);
         returns the number of leaves waiting for a split."""
         self.torch.cuda.current_stream(self.device).synchronize()
-        return cvx.cvx_stroke_begin(self.ctx, canvas_id, stamps, rgb, sigma, radius, k_refine)
+        return cvx.cvx_stroke_begin(self.ctx, canvas_id, stamps, rgb, sigma, radius, k_refine,
+                                    coarsen)
 
     def stroke_step(self, canvas_id):
         """One deferred refinement level of the stroke (cvx_stroke_step)."""

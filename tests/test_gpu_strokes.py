@@ -169,6 +169,49 @@ def test_stroke_into_a_coarse_canvas(sess, fmt):
         _same_leaves(_device_pool(sess, 0, cv)[1], want, fmt)
 
 
+@pytest.mark.parametrize("fmt", [LEAF_F64, LEAF_RGBA8_F16])
+def test_coarsening_strokes_match_oracle(sess, fmt):
+    """Strokes with coarsen = 1 over a uniform canvas: after the splits, the
+    steps merge cells whose 8 children are identical leaves, one level per
+    step, and the pool ends on the oracle's stroke followed by its lossless
+    merge; the records equal a fresh upload's and the image the oracle's."""
+    from paper_1704_02724_amd import cvx
+    cv = trees.from_refinement(1, 8, lambda d, c: d < 2, lambda d, c: (0.3, 0.6, 0.2, 0.5), fmt)
+    st = gen_strokes(np.random.Generator(np.random.PCG64(97)), 3, -4, -3)
+    k = 4.0
+    sess.upload(0, cv)
+    want = so.canonical_from_pool(cv.nodes, cv.leaves, 1)
+    n0 = cvx.cvx_pool_nodes(sess.ctx, 0)
+    for i in range(st.n):
+        args = _stroke_args(cv, st, i, k)
+        painted, split = so.apply_stroke(want, fmt, *args)
+        want, merged = so.merge_uniform(painted, fmt, cv.root_edge, cv.origin, st.stamps_of(i))
+        p = sess.stroke_begin(0, st.stamps_of(i), st.rgb[i], st.sigma[i], st.radius[i], k,
+                              coarsen=True)
+        steps = 0
+        while p:
+            p = sess.stroke_step(0)
+            steps += 1
+            assert steps <= 2 * cv.max_depth
+        host, got = _device_pool(sess, 0, cv)
+        print(f"stroke {i}: {len(split)} splits, {len(merged)} merges, {steps} steps", flush=True)
+        assert merged
+        _same_leaves(got, want, fmt)
+    sess.upload(1, host)
+    np.testing.assert_array_equal(cvx.cvx_read_records(sess.ctx, 0),
+                                  cvx.cvx_read_records(sess.ctx, 1))
+    views = _views(np.random.Generator(np.random.PCG64(97)), 2, 32, 24)
+    variant, tol = ("fp64_plain", 1e-6) if fmt == LEAF_F64 else ("fp32_rebased", 1e-3)
+    ids = all_ray_ids(views)
+    orc = oracle.render([host], views, ids, max_leaves=1024)
+    gpu = sess.trace(views, ids, 1024, variant)
+    cmp = compare_traces(orc, gpu, 1024)
+    assert cmp["seq_mismatch"] == 0, cmp
+    img = sess.render(views, variant).cpu().numpy()
+    assert rgba_err(img, orc["rgba"], cmp["ok_mask"]) <= tol
+    assert cvx.cvx_pool_nodes(sess.ctx, 0) >= n0
+
+
 def test_stroke_errors_edits_and_overlap(sess):
     from paper_1704_02724_amd import cvx
     k = 4.0

@@ -12,6 +12,10 @@
   are untouched in both).
 * The deferred passes (immediate paint, then one level of splits at a time)
   end on the result of the stroke applied at once.
+* The lossless coarsening: a uniform canvas under a stroke that covers it
+  collapses to its roots with the optical depth doubled per level; on
+  stroked canvases it leaves no mergeable cell and the FP64 oracle renders
+  the coarsened canvas like the uncoarsened one.
 """
 import math
 
@@ -137,3 +141,50 @@ def test_deferred_passes_end_on_the_stroke_at_once(fmt):
             cur.update(painted)
         assert 0 < passes <= cv.max_depth
         assert cur == want
+
+
+def _pool_from(leaves, R, max_depth, fmt):
+    """A host pool of a canonical dict (F64 leaves), for the render oracle."""
+    cells = set(leaves)
+    inner = {(d - k, x >> k, y >> k, z >> k) for (d, x, y, z) in cells for k in range(1, d + 1)}
+    return trees.from_refinement(R, max_depth, lambda d, c: (d, *c) in inner,
+                                 lambda d, c: leaves[(d, *c)], fmt)
+
+
+def test_merge_collapses_a_uniform_canvas():
+    cv = trees.from_refinement(2, 4, lambda d, c: d < 3, lambda d, c: (0.25, 0.5, 0.75, 0.125),
+                               LEAF_F64)
+    leaves = _canon(cv)
+    big = np.array([[0.5, 0.5, 0.5, 2.0]])            # covers the whole canvas
+    out, merged = so.merge_uniform(leaves, so.F64, cv.root_edge, cv.origin, big)
+    assert set(out) == {(0, x, y, z) for x in range(2) for y in range(2) for z in range(2)}
+    assert all(p == (0.25, 0.5, 0.75, 0.125 * 8) for p in out.values())
+    assert len(merged) == 8 * (1 + 8 + 64)             # depth 2, 1 and 0 cells
+
+
+@pytest.mark.parametrize("fmt", [LEAF_F64, LEAF_RGBA8_F16])
+def test_merge_after_strokes_is_lossless_and_complete(fmt):
+    from oracle import oracle
+    cv = trees.from_refinement(1, 8, lambda d, c: d < 2, lambda d, c: (0.3, 0.6, 0.2, 0.5), fmt)
+    st = gen_strokes(np.random.Generator(np.random.PCG64(14)), 2, -4, -3)
+    k = 4.0
+    leaves = _canon(cv)
+    for i in range(st.n):
+        args = (cv.R, cv.max_depth, cv.root_edge, cv.origin, st.stamps_of(i), st.rgb[i],
+                st.sigma[i], st.radius[i], k)
+        painted, _ = so.apply_stroke(leaves, fmt, *args)
+        merged, cells = so.merge_uniform(painted, fmt, cv.root_edge, cv.origin, st.stamps_of(i))
+        assert cells and len(merged) < len(painted)
+        # no mergeable cell left under the stroke
+        again, more = so.merge_uniform(merged, fmt, cv.root_edge, cv.origin, st.stamps_of(i))
+        assert not more and again == merged
+        if fmt == LEAF_F64:
+            # the render oracle sees the same canvas
+            rng = np.random.Generator(np.random.PCG64(15 + i))
+            from helpers import random_rays, ray_views
+            vs = ray_views(*random_rays(rng, 300))
+            a = oracle.render([_pool_from(painted, 1, cv.max_depth, fmt)], vs)
+            b = oracle.render([_pool_from(merged, 1, cv.max_depth, fmt)], vs)
+            np.testing.assert_allclose(b["rgba"], a["rgba"], atol=1e-12)
+            assert b["n_leaves"].sum() < a["n_leaves"].sum()
+        leaves = merged
