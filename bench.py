@@ -201,19 +201,26 @@ def edit_bench(sess, cv, n_paint, n_refine, n_coarsen, seed):
                 nodes=int(cv.n_nodes))
 
 
+def cvx_nodes(sess, canvas_id):
+    from paper_1704_02724_amd import cvx
+    return cvx.cvx_pool_nodes(sess.ctx, canvas_id)
+
+
 def stroke_bench(sess, cv, seed):
     """Times brush strokes with deferred refinement (cvx_stroke_begin, then one
-    cvx_stroke_step per frame until no leaf waits) on a copy of the canvas:
-    seeded strokes of a fine, a middle and a large brush radius."""
+    cvx_stroke_step per frame until nothing waits) on a copy of the canvas:
+    seeded strokes of a fine, a middle and a large brush radius, and one large
+    coarsening stroke (its merges follow its splits)."""
     from canvasgen.strokes import gen_strokes
     torch = sess.torch
     sess.upload(9, cv)
     torch.cuda.synchronize()
     out = []
-    for j, lg in enumerate((-16, -10, -5)):
+    for j, (lg, coarsen) in enumerate(((-16, False), (-10, False), (-5, False), (-6, True))):
         st = gen_strokes(np.random.Generator(np.random.PCG64(seed + j)), 1, lg, lg)
         t = time.perf_counter()
-        p = sess.stroke_begin(9, st.stamps_of(0), st.rgb[0], st.sigma[0], st.radius[0], 4.0)
+        p = sess.stroke_begin(9, st.stamps_of(0), st.rgb[0], st.sigma[0], st.radius[0], 4.0,
+                              coarsen=coarsen)
         frames = [round((time.perf_counter() - t) * 1e3, 2)]
         waiting = [p]
         while p:
@@ -221,8 +228,8 @@ def stroke_bench(sess, cv, seed):
             p = sess.stroke_step(9)
             frames.append(round((time.perf_counter() - t) * 1e3, 2))
             waiting.append(p)
-        row = dict(radius_log2=lg, stamps=int(len(st.stamps_of(0))), frame_ms=frames,
-                   waiting=waiting, splits=int(sum(waiting)))
+        row = dict(radius_log2=lg, coarsen=coarsen, stamps=int(len(st.stamps_of(0))),
+                   frame_ms=frames, waiting=waiting, nodes=cvx_nodes(sess, 9))
         log(f"stroke: {row}")
         out.append(row)
     sess.free(9)
