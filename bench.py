@@ -78,6 +78,8 @@ def build_workload(name, threads):
         return configs.depth24(k=10.0, threads=threads)
     if name == "depth30":
         return configs.depth30(threads=threads)
+    if name == "depth30_k10":
+        return configs.depth30(k=10.0, threads=threads)
     if name == "tiny":
         from canvasgen import LEAF_RGBA8_F16
         return configs.tiny(leaf_format=LEAF_RGBA8_F16)

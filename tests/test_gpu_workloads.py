@@ -83,6 +83,27 @@ def test_depth30_sampled(sess, depth30, variant):
     assert err <= 1e-3
 
 
+def test_depth30_k10_sampled(sess):
+    """The depth-30 strokes with refine factor 10: the fine strokes reach the
+    depth-30 limit (cells of edge 2^-30), which the k = 4 canvas stops one
+    level short of.  Rays here cross about 550 leaves, most of them of edge
+    2^-30, so most rays come within 1e-12 of some leaf face and are flagged;
+    the sample is sized so that thousands remain for the sequence check."""
+    w = configs.depth30(k=10.0)
+    assert int(w.canvases[0].max_depth) == 30
+    ids = sample_ray_ids(w.views, 16384, 3032)
+    cmp, err, orc, _ = _sampled(sess, w, ids, "fp32_rebased")
+    deep = int((orc["leaf_depth"] == 30).any(axis=1).sum())
+    print(f"depth30 k=10: {cmp['n']} rays, flagged {cmp['flagged']}, "
+          f"mismatch {cmp['seq_mismatch']} (flagged included {cmp['seq_mismatch_all']}), "
+          f"rgba err {err:.3g}, mean leaves {orc['n_leaves'].mean():.1f}, "
+          f"max {orc['n_leaves'].max()}, rays through depth-30 leaves {deep}")
+    assert deep > 0
+    assert cmp["n"] - cmp["flagged"] >= 2048
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= 1e-3
+
+
 def test_depth30_naive_fails_visibly(sess, depth30):
     """The canvas-global FP32 traversal cannot resolve depth-30 cells."""
     ids = sample_ray_ids(depth30.views, 8192, 3031)
