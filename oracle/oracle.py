@@ -136,7 +136,7 @@ def render(canvases, views, ray_ids=None, eps_face=EPS_FACE, max_leaves=0, threa
         out["leaf_depth"] = np.zeros((n, max_leaves), np.uint8)
     p = lambda k: out[k].ctypes.data if k in out else None  # noqa: E731
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = min(16, os.cpu_count() or 1)
     rc = lib.orc_render(cs, len(canvases), vs, len(views), ids_ptr, n, eps_face, max_leaves,
                         p("rgba"), p("flags"), p("n_leaves"), p("alg_bytes"), p("chord"),
                         p("sum_len"), p("leaf_ids"), p("leaf_len"), p("leaf_depth"), int(threads))
