@@ -38,11 +38,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of what the cast kernel is compiled from: its sources and the
+    compiler flags."""
     import hashlib
+    from paper_1704_02724_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
     for f in ("paper_1704_02724_amd/csrc/cvx_cast.hip", "paper_1704_02724_amd/csrc/cvx_internal.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
