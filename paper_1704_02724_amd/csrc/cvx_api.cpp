@@ -1,4 +1,5 @@
-// C-ABI entry points of libcvx: context, pool upload, render, errors.
+// C-ABI entry points of libcvx: context, pool upload, render and launch
+// autotuning, pool edits and brush strokes, diagnostics, errors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
