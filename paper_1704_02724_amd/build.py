@@ -22,7 +22,7 @@ HIPCC_FLAGS = [
     # machine-level loop-invariant code motion lifts constants of the per-ray
     # setup out of the persistent tile loop, where they stay live through the
     # whole traversal; without it the FP32 render kernel needs no scratch
-    # (63 VGPRs instead of 64 plus 12 bytes of spills per lane) with the same
+    # (62-63 VGPRs instead of 64 plus 8-12 bytes of spills per lane) with the same
     # hot-loop instructions
     "-mllvm", "-disable-machine-licm",
     # the render loop is bound by vector instruction issue; the scheduler's
