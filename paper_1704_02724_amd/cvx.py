@@ -37,11 +37,17 @@ CVX_VARIANT_FP16_CELL_LOCAL = 4
 VARIANTS = {"fp32_rebased": 0, "fp64_plain": 1, "fp32_naive": 2, "fp32_cell_local": 3,
             "fp16_cell_local": 4}
 
+CVX_MAX_CANVASES = 64
+CVX_MAX_DEPTH = 30
+CVX_MAX_VIEWS = 4096
+
 CVX_RAYFLAG_STEP_CAP = 1
 CVX_RAYFLAG_FP64_EXIT = 2
 CVX_RAYFLAG_BAD_LINK = 4
 
 CVX_STAT_NAMES = ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase", "steps", "slots"]
+(CVX_STAT_RAYS, CVX_STAT_LEAVES, CVX_STAT_OUTER, CVX_STAT_DESCENT, CVX_STAT_FP64_EXIT,
+ CVX_STAT_REBASE, CVX_STAT_STEPS, CVX_STAT_SLOTS) = range(8)
 CVX_STAT_COUNT = 8
 
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",

@@ -117,3 +117,14 @@ def test_create_without_gpu_fails_cleanly(cvx):
         pytest.skip("a GPU is present")
     with pytest.raises(cvx.CvxError):
         cvx.cvx_create(0, 0)
+
+
+def test_binding_constants_match_the_header(cvx):
+    hdr = open(os.path.join(ROOT, "include", "cvx.h")).read()
+    defines = re.findall(r"^#define (CVX_\w+) \(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?", hdr,
+                         flags=re.M)
+    assert len(defines) > 20
+    missing = [n for n, _ in defines if not hasattr(cvx, n)]
+    assert not missing, missing
+    for name, value in defines:
+        assert getattr(cvx, name) == int(value, 0), name

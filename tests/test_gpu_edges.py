@@ -3,7 +3,8 @@ by ray: rays exactly along an axis or inside a coordinate plane (zero
 direction components), a canvas that is one leaf, root arrays whose roots are
 leaves (steps through the root array) up to the largest root array, optical
 depths of zero and near the half-precision maximum, a stop opacity reached in
-the first segment, the largest view count, and the empty calls."""
+the first segment, the largest view count, every canvas slot at once, and
+the empty calls."""
 import numpy as np
 import pytest
 
@@ -149,3 +150,25 @@ def test_largest_view_count_and_empty_calls(sess):
     with pytest.raises(cvx.CvxError) as e:
         sess.trace(views[:1], np.zeros(0, np.uint64), 4)               # no rays
     assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+
+
+def test_every_canvas_slot(sess):
+    """CVX_MAX_CANVASES (64) pools resident at once, one view on each, in one
+    launch; slot 64 is refused and leaves the others unchanged."""
+    from paper_1704_02724_amd import cvx
+    canvases = [trees.random_tree(1 + i % 3, 3 + i % 3, seed=200 + i, max_nodes=1500,
+                                  leaf_format=LEAF_RGBA8_F16)
+                for i in range(cvx.CVX_MAX_CANVASES)]
+    rng = np.random.Generator(np.random.PCG64(200))
+    views = []
+    for i, c in enumerate(canvases):
+        e = rng.uniform(-0.5, 1.5, 3)
+        views.append(make_view(e, rng.uniform(0.3, 0.7, 3) - e, 0.5, 6, 5, canvas_id=i))
+    views = _offsets(views)
+    _parity(sess, canvases, views)
+    before = sess.render(views, "fp32_rebased").cpu().numpy()
+    with pytest.raises(cvx.CvxError) as e:
+        sess.upload(cvx.CVX_MAX_CANVASES, canvases[0])
+    assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+    after = sess.render(views, "fp32_rebased").cpu().numpy()
+    np.testing.assert_array_equal(before, after)
