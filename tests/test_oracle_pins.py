@@ -256,6 +256,28 @@ def test_near_face_flags():
     assert out["flags"][3] == 0
 
 
+def test_near_face_flags_at_entry_only_and_exit_only():
+    """A single cell isolates the two checks of the face band: a ray that
+    enters 5e-13 from an edge of the cell and leaves far from every other
+    face is flagged by its entry point alone, and one that enters far from
+    the edges and leaves 5e-13 from one by its exit point alone; the same rays
+    1e-9 away from the edge are not flagged."""
+    cv = trees.single_cell((0.5, 0.5, 0.5), 1.0)
+    d = np.array([0.3, 0.0, 1.0]) / math.hypot(0.3, 1.0)
+    t_in = 1.0 / d[2]                                   # from z = -1 to the face z = 0
+
+    def ray(x_at_entry):
+        return (x_at_entry - t_in * d[0], 0.5, -1.0)
+
+    eyes = [ray(5e-13), ray(1e-9), ray(0.7 - 5e-13), ray(0.7 - 1e-9)]
+    out = oracle.render([cv], ray_views(eyes, [d] * 4))
+    assert out["flags"][0] & oracle.FLAG_NEAR_FACE      # entry 5e-13 from the face x = 0
+    assert out["flags"][1] == 0
+    assert out["flags"][2] & oracle.FLAG_NEAR_FACE      # exit 5e-13 from the face x = 1
+    assert out["flags"][3] == 0
+    assert np.all(out["n_leaves"] == 1)
+
+
 def test_algorithmic_bytes_hand_count():
     # uniform depth-2 lattice, axis ray through four cells: descend 2 levels to
     # the first leaf, then sibling, outer (parent boundary), sibling steps
