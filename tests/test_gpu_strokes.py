@@ -259,3 +259,27 @@ def test_stroke_errors_edits_and_overlap(sess):
     while p:
         p = sess.stroke_step(0)
     _same_leaves(_device_pool(sess, 0, cv)[1], want, fmt)
+
+
+@pytest.mark.parametrize("stamp,radius", [((0.75, 0.25, 0.25, 0.25), 0.25),
+                                          ((0.7, 0.7, 0.7, 2.0 ** -4), 2.0 ** -4)])
+def test_exact_rule_boundaries(sess, stamp, radius):
+    """A stamp sphere that only touches leaf boxes (box distance equal to its
+    radius, exact in FP64) and a brush whose radius / k is an exact leaf edge:
+    the GPU takes the strict decisions the oracle takes, leaf for leaf."""
+    cv = trees.from_refinement(1, 10, lambda d, c: d < 1, lambda d, c: (0.2, 0.4, 0.6, 1.0),
+                               LEAF_F64)
+    sess.upload(0, cv)
+    stamps = np.array([stamp], np.float64)
+    rgb, sigma, k = (1.0, 0.0, 0.0), 10.0, 4.0
+    pending = sess.stroke_begin(0, stamps, rgb, sigma, radius, k)
+    steps = 0
+    while pending and steps < 2 * cv.max_depth + 2:
+        pending = sess.stroke_step(0)
+        steps += 1
+    assert pending == 0
+    _, got = _device_pool(sess, 0, cv)
+    want, _ = so.apply_stroke(so.canonical_from_pool(cv.nodes, cv.leaves, cv.R), so.F64, cv.R,
+                              cv.max_depth, cv.root_edge, cv.origin, stamps, rgb, sigma,
+                              radius, k)
+    _same_leaves(got, want, LEAF_F64)

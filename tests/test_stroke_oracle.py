@@ -188,3 +188,28 @@ def test_merge_after_strokes_is_lossless_and_complete(fmt):
             np.testing.assert_allclose(b["rgba"], a["rgba"], atol=1e-12)
             assert b["n_leaves"].sum() < a["n_leaves"].sum()
         leaves = merged
+
+
+def test_exact_boundaries_of_the_rules():
+    """Exact dyadic cases of the two strict inequalities of the rules (Sec.
+    5.2 read as in the builder): a leaf is split only while its edge exceeds
+    radius / k, so a brush of radius 2^-4 with k = 4 stops at edge 2^-6 =
+    radius / k; and a stamp reaches a leaf only when the leaf's box lies at a
+    distance below its radius, so a sphere that only touches a box (distance
+    equal to the radius, exact in FP64) leaves that leaf alone."""
+    cv = trees.from_refinement(1, 10, lambda d, c: d < 1, lambda d, c: (0.2, 0.4, 0.6, 1.0),
+                               LEAF_F64)
+    leaves = _canon(cv)
+    r = 2.0 ** -4
+    # touches the box of leaf (1, 0, 0, 0) = [0, 0.5]^3 from x = 0.75, inside leaf (1, 1, 0, 0)
+    stamp = np.array([[0.75, 0.25, 0.25, 0.25]])
+    out, split = so.apply_stroke(leaves, so.F64, 1, 10, 1.0, (0.0, 0.0, 0.0), stamp,
+                                 (1.0, 0.0, 0.0), 10.0, 0.25, 4.0)
+    assert out[(1, 0, 0, 0)] == leaves[(1, 0, 0, 0)] and (1, 0, 0, 0) not in split
+    assert (1, 1, 0, 0) in split
+    # a brush of radius 2^-4, one stamp inside leaf (1, 1, 1, 1)
+    stamp = np.array([[0.7, 0.7, 0.7, r]])
+    out, split = so.apply_stroke(leaves, so.F64, 1, 10, 1.0, (0.0, 0.0, 0.0), stamp,
+                                 (1.0, 0.0, 0.0), 10.0, r, 4.0)
+    assert max(d for (d, _, _, _) in out) == 6
+    assert max(d for (d, _, _, _) in split) == 5
