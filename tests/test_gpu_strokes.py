@@ -261,13 +261,15 @@ def test_stroke_errors_edits_and_overlap(sess):
     _same_leaves(_device_pool(sess, 0, cv)[1], want, fmt)
 
 
-@pytest.mark.parametrize("stamp,radius", [((0.75, 0.25, 0.25, 0.25), 0.25),
-                                          ((0.7, 0.7, 0.7, 2.0 ** -4), 2.0 ** -4)])
-def test_exact_rule_boundaries(sess, stamp, radius):
+@pytest.mark.parametrize("stamp,radius,depth", [((0.75, 0.25, 0.25, 0.25), 0.25, 10),
+                                                ((0.7, 0.7, 0.7, 2.0 ** -4), 2.0 ** -4, 10),
+                                                ((0.75, 0.25, 0.25, 0.5), 0.5, 1)])
+def test_exact_rule_boundaries(sess, stamp, radius, depth):
     """A stamp sphere that only touches leaf boxes (box distance equal to its
-    radius, exact in FP64) and a brush whose radius / k is an exact leaf edge:
-    the GPU takes the strict decisions the oracle takes, leaf for leaf."""
-    cv = trees.from_refinement(1, 10, lambda d, c: d < 1, lambda d, c: (0.2, 0.4, 0.6, 1.0),
+    radius, exact in FP64), a brush whose radius / k is an exact leaf edge,
+    and a sphere through a leaf centre on a canvas that cannot refine: the GPU
+    takes the decisions the oracle takes, leaf for leaf."""
+    cv = trees.from_refinement(1, depth, lambda d, c: d < 1, lambda d, c: (0.2, 0.4, 0.6, 1.0),
                                LEAF_F64)
     sess.upload(0, cv)
     stamps = np.array([stamp], np.float64)

@@ -191,12 +191,13 @@ def test_merge_after_strokes_is_lossless_and_complete(fmt):
 
 
 def test_exact_boundaries_of_the_rules():
-    """Exact dyadic cases of the two strict inequalities of the rules (Sec.
-    5.2 read as in the builder): a leaf is split only while its edge exceeds
-    radius / k, so a brush of radius 2^-4 with k = 4 stops at edge 2^-6 =
-    radius / k; and a stamp reaches a leaf only when the leaf's box lies at a
-    distance below its radius, so a sphere that only touches a box (distance
-    equal to the radius, exact in FP64) leaves that leaf alone."""
+    """Exact dyadic cases of the inequalities of the rules (Sec. 5.1-5.2 read
+    as in the builder): a leaf is split only while its edge exceeds radius /
+    k, so a brush of radius 2^-4 with k = 4 stops at edge 2^-6 = radius / k;
+    a stamp reaches a leaf only when the leaf's box lies at a distance below
+    its radius, so a sphere that only touches a box (distance equal to the
+    radius, exact in FP64) leaves that leaf alone; and a leaf whose centre
+    lies on a stamp's sphere takes the stroke."""
     cv = trees.from_refinement(1, 10, lambda d, c: d < 1, lambda d, c: (0.2, 0.4, 0.6, 1.0),
                                LEAF_F64)
     leaves = _canon(cv)
@@ -213,3 +214,15 @@ def test_exact_boundaries_of_the_rules():
                                  (1.0, 0.0, 0.0), 10.0, r, 4.0)
     assert max(d for (d, _, _, _) in out) == 6
     assert max(d for (d, _, _, _) in split) == 5
+    # a leaf takes the stroke when its centre lies in a stamp, the sphere's
+    # surface included: on a canvas that cannot refine further, a stamp of
+    # radius 0.5 at distance exactly 0.5 from the centre of leaf (1, 0, 0, 0)
+    flat = trees.from_refinement(1, 1, lambda d, c: d < 1, lambda d, c: (0.2, 0.4, 0.6, 1.0),
+                                 LEAF_F64)
+    fl = _canon(flat)
+    stamp = np.array([[0.75, 0.25, 0.25, 0.5]])
+    out, split = so.apply_stroke(fl, so.F64, 1, 1, 1.0, (0.0, 0.0, 0.0), stamp,
+                                 (1.0, 0.0, 0.0), 10.0, 0.5, 4.0)
+    assert not split
+    assert out[(1, 0, 0, 0)] != fl[(1, 0, 0, 0)]      # centre on the sphere: painted
+    assert out[(1, 0, 1, 0)] == fl[(1, 0, 1, 0)]      # overlapped, centre outside
