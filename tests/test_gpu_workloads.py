@@ -1,7 +1,8 @@
 """GPU parity at full workload sizes, on seeded ray samples the oracle traces.
 
-The full image is rendered in the launch configuration the benchmark times;
-sampled pixels are compared with the oracle, and the same sample is traced to
+The full image is rendered in the launch configuration the benchmark times
+(the launch shape cvx_autotune picks, replayed as a HIP graph); sampled
+pixels are compared with the oracle, and the same sample is traced to
 compare leaf sequences.
 """
 import numpy as np
@@ -44,7 +45,8 @@ def _sampled(sess, w, ids, variant):
     gpu = sess.trace(w.views, ids, ML, variant)
     assert np.all((gpu["flags"] & 0x5) == 0)
     cmp = compare_traces(orc, gpu, ML, len_atol=1e-3)
-    img = sess.render(w.views, variant, use_graph=True).cpu().numpy()
+    tuning, _ = sess.autotune(w.views, variant, reps=1)
+    img = sess.render(w.views, variant, use_graph=True, **tuning).cpu().numpy()
     vi = (ids >> np.uint64(32)).astype(np.int64)
     px = (ids & np.uint64(0xFFFFFFFF)).astype(np.int64)
     offs = np.array([v["out_offset_px"] for v in w.views], np.int64)
