@@ -128,3 +128,16 @@ def test_binding_constants_match_the_header(cvx):
     assert not missing, missing
     for name, value in defines:
         assert getattr(cvx, name) == int(value, 0), name
+
+
+def test_binding_fails_loudly_without_the_library():
+    """No fallback: with libcvx.so absent the binding (and so the session,
+    the tests and the benchmark) cannot be imported."""
+    import subprocess
+    import sys
+    code = ("import paper_1704_02724_amd.build as b; b.LIB_PATH = '/nonexistent/libcvx.so'; "
+            "import paper_1704_02724_amd.cvx")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "/nonexistent/libcvx.so is not built" in r.stderr
