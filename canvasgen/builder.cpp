@@ -156,13 +156,27 @@ struct Builder {
   }
 };
 
-// Result handle handed back to the caller.
+// The painted trees of one build, kept until they are emitted: the tree
+// above the split depth and one pool per depth-S subtree.
+template <class T>
+struct Painted {
+  uint32_t R = 1, P0 = 8;
+  Pool<T> top;
+  std::vector<Pool<T>> subs;
+  std::vector<uint64_t> sub_leaves;  // leaves per subtree
+};
+
+// Result handle handed back to the caller: sizes after the build, the pool
+// itself after emission into the caller's arrays.
 struct Result {
-  std::vector<uint32_t> nodes;   // 2 per node
-  std::vector<uint8_t> leaves;   // packed leaf records
   uint64_t n_nodes = 0, n_leaves = 0;
-  uint32_t max_depth_seen = 0;
-  std::vector<uint64_t> depth_hist;  // leaves per depth
+  int fmt = 0;
+  Painted<float>* pf = nullptr;
+  Painted<double>* pd = nullptr;
+  ~Result() {
+    delete pf;
+    delete pd;
+  }
 };
 
 uint16_t f32_to_f16(float f) {
@@ -188,9 +202,9 @@ uint16_t f32_to_f16(float f) {
 }
 
 template <class T>
-void emit_leaf(Result& res, uint64_t li, const T* c, int fmt) {
+void emit_leaf(uint8_t* leaves, uint64_t li, const T* c, int fmt) {
   if (fmt == 0) {
-    uint8_t* p = &res.leaves[li * 8];
+    uint8_t* p = &leaves[li * 8];
     for (int ch = 0; ch < 3; ++ch) {
       double v = std::min(std::max((double)c[ch], 0.0), 1.0);
       p[ch] = (uint8_t)std::lrint(255.0 * v);
@@ -202,7 +216,7 @@ void emit_leaf(Result& res, uint64_t li, const T* c, int fmt) {
     p[6] = p[7] = 0;
   } else {
     double v[4] = {(double)c[0], (double)c[1], (double)c[2], (double)c[3]};
-    std::memcpy(&res.leaves[li * 32], v, 32);
+    std::memcpy(&leaves[li * 32], v, 32);
   }
 }
 
@@ -210,8 +224,8 @@ void emit_leaf(Result& res, uint64_t li, const T* c, int fmt) {
 std::atomic<int> g_verbose{0};
 
 template <class T>
-int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Strokes& st, int fmt,
-          Result& res) {
+int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Strokes& st,
+          Painted<T>& out, uint64_t& n_nodes, uint64_t& n_leaves) {
   Builder<T> B;
   B.R = R; B.D = D; B.k = k; B.st = st;
   B.root_edge = 1.0 / (double)R;
@@ -251,7 +265,9 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
 
   // Phase 2: independent subtrees rooted at depth S.
   const size_t nsub = B.seeds.size();
-  std::vector<Pool<T>> subs(nsub);
+  std::vector<Pool<T>>& subs = out.subs;
+  subs.assign(nsub, Pool<T>());
+  out.sub_leaves.assign(nsub, 0);
   if (nsub) {
     // Stroke lists per subtree (strokes >= s0 whose stamps overlap X).
     std::vector<std::vector<int>> lists(nsub);
@@ -311,6 +327,9 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
           for (int64_t j = st.off[s]; j < st.off[s + 1]; ++j)
             B.apply_stamp(P, 0, (int)B.S, sd.ix, sd.iy, sd.iz, s, st.stamps[j], 0xffffffffu,
                           [](uint32_t) {});
+        uint64_t nl = 0;
+        for (uint32_t c : P.child) nl += (c & LEAF) ? 1u : 0u;
+        out.sub_leaves[i] = nl;
         const size_t d = done.fetch_add(1) + 1;
         if (g_verbose && nsub >= 10 && d % (nsub / 10) == 0)
           std::fprintf(stderr, "[canvasgen] painted %zu / %zu subtrees\n", d, nsub);
@@ -323,8 +342,7 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
     for (auto& t : th) t.join();
   }
 
-  if (g_verbose) std::fprintf(stderr, "[canvasgen] emitting the pool\n");
-  // Emit in depth-first group order.  Count first.
+  // sizes of the pool in depth-first group order
   uint64_t nn = P0, nl = 0;
   {
     // top tree: every non-root node is in a group; subtree roots are top nodes
@@ -333,56 +351,134 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
     for (auto& P : subs) nn += P.size() - 1;
   }
   if (nn >= (uint64_t)LEAF) return -3;
-  res.n_nodes = nn;
-  res.nodes.assign(2 * nn, 0);
-  res.depth_hist.assign(64, 0);
-  // leaf count
   for (uint32_t i = 0; i < top.size(); ++i)
     if ((top.child[i] & LEAF) && top.ext[i] < 0 && (i >= P0 || i < R3)) ++nl;
-  for (auto& P : subs)
-    for (uint32_t i = 0; i < P.size(); ++i)
-      if (P.child[i] & LEAF) ++nl;
-  res.n_leaves = nl;
-  res.leaves.assign(nl * (fmt == 0 ? 8 : 32), 0);
+  for (uint64_t c : out.sub_leaves) nl += c;
+  out.R = R;
+  out.P0 = P0;
+  out.top = std::move(top);
+  n_nodes = nn;
+  n_leaves = nl;
+  return 0;
+}
 
-  uint64_t next_node = P0, next_leaf = 0;
+// Depth-first emission of one tree below `src` of pool P (dst: its output
+// node id), allocating groups from next_node and leaves from next_leaf in
+// the order a preorder walk meets them.  A top-tree node standing for a
+// depth-S subtree is emitted from that subtree's pool unless `stop_at_subs`
+// asks for it to be handed to on_sub instead (which then reserves the
+// subtree's contiguous node and leaf ranges).
+template <class T, class OnSub>
+void emit_tree(const Painted<T>& W, const Pool<T>* P, uint32_t src, uint64_t dst,
+               uint32_t parent_dst, int d, uint32_t* nodes, uint8_t* leaves, int fmt,
+               uint64_t& next_node, uint64_t& next_leaf, uint64_t* hist, uint32_t& md,
+               bool stop_at_subs, OnSub&& on_sub) {
   struct Frame { const Pool<T>* P; uint32_t src; uint64_t dst; uint32_t parent_dst; int d; };
   std::vector<Frame> stack;
-  auto emit = [&](const Pool<T>* P, uint32_t src, uint64_t dst, uint32_t parent_dst, int d) {
-    stack.push_back({P, src, dst, parent_dst, d});
-    while (!stack.empty()) {
-      Frame f = stack.back();
-      stack.pop_back();
-      const Pool<T>* Q = f.P;
-      uint32_t s2 = f.src;
-      if (Q == &top && top.ext[s2] >= 0) {
-        Q = &subs[top.ext[s2]];
-        s2 = 0;
+  stack.push_back({P, src, dst, parent_dst, d});
+  while (!stack.empty()) {
+    Frame f = stack.back();
+    stack.pop_back();
+    const Pool<T>* Q = f.P;
+    uint32_t s2 = f.src;
+    nodes[2 * f.dst + 1] = f.parent_dst;
+    if (Q == &W.top && W.top.ext[s2] >= 0) {
+      const int32_t e = W.top.ext[s2];
+      if (stop_at_subs) {
+        on_sub(e, f.dst, f.d);
+        continue;
       }
-      res.nodes[2 * f.dst + 1] = f.parent_dst;
-      uint32_t c = Q->child[s2];
-      if (c & LEAF) {
-        res.nodes[2 * f.dst] = LEAF | (uint32_t)next_leaf;
-        emit_leaf<T>(res, next_leaf, &Q->col[4 * (size_t)s2], fmt);
-        ++next_leaf;
-        res.depth_hist[f.d]++;
-        res.max_depth_seen = std::max(res.max_depth_seen, (uint32_t)f.d);
-      } else {
-        uint64_t g = next_node;
-        next_node += 8;
-        res.nodes[2 * f.dst] = (uint32_t)g;
-        for (int o = 7; o >= 0; --o)
-          stack.push_back({Q, c + (uint32_t)o, g + (uint64_t)o, (uint32_t)f.dst, f.d + 1});
-      }
+      Q = &W.subs[e];
+      s2 = 0;
     }
-  };
-  for (uint32_t r = 0; r < R3; ++r) emit(&top, r, r, NONE, 0);
+    uint32_t c = Q->child[s2];
+    if (c & LEAF) {
+      nodes[2 * f.dst] = LEAF | (uint32_t)next_leaf;
+      emit_leaf<T>(leaves, next_leaf, &Q->col[4 * (size_t)s2], fmt);
+      ++next_leaf;
+      hist[f.d]++;
+      md = std::max(md, (uint32_t)f.d);
+    } else {
+      uint64_t g = next_node;
+      next_node += 8;
+      nodes[2 * f.dst] = (uint32_t)g;
+      for (int o = 7; o >= 0; --o)
+        stack.push_back({Q, c + (uint32_t)o, g + (uint64_t)o, (uint32_t)f.dst, f.d + 1});
+    }
+  }
+}
+
+// Emission into the caller's arrays.  A preorder walk allocates the groups
+// of a subtree's descendants contiguously (the walk finishes a subtree before
+// it pops anything pushed earlier), so the walk of the top tree reserves each
+// depth-S subtree's node and leaf ranges and the subtrees are emitted in
+// parallel into them: the output is the sequential walk's, byte for byte.
+template <class T>
+int emit(const Painted<T>& W, uint64_t nn, uint64_t nl, uint32_t* nodes, uint8_t* leaves, int fmt,
+         uint64_t* hist_out, uint32_t* md_out, int nthreads) {
+  if (g_verbose) std::fprintf(stderr, "[canvasgen] emitting the pool\n");
+  struct Task { int32_t sub; uint64_t dst, node_base, leaf_base; int d; };
+  std::vector<Task> tasks;
+  uint64_t next_node = W.P0, next_leaf = 0;
+  std::vector<uint64_t> hist(64, 0);
+  uint32_t md = 0;
+  const uint32_t R3 = W.R * W.R * W.R;
+  for (uint32_t r = 0; r < R3; ++r)
+    emit_tree<T>(W, &W.top, r, r, NONE, 0, nodes, leaves, fmt, next_node, next_leaf, hist.data(),
+                 md, true, [&](int32_t e, uint64_t dst, int d) {
+                   const Pool<T>& P = W.subs[e];
+                   if (P.child[0] & LEAF) {  // an unrefined subtree root: one leaf
+                     nodes[2 * dst] = LEAF | (uint32_t)next_leaf;
+                     emit_leaf<T>(leaves, next_leaf, &P.col[0], fmt);
+                     ++next_leaf;
+                     hist[d]++;
+                     md = std::max(md, (uint32_t)d);
+                     return;
+                   }
+                   tasks.push_back({e, dst, next_node, next_leaf, d});
+                   next_node += P.size() - 1;
+                   next_leaf += W.sub_leaves[e];
+                 });
   // padding root slots: leaves sharing leaf 0, never referenced
-  for (uint32_t r = R3; r < P0; ++r) {
-    res.nodes[2 * r] = LEAF | 0u;
-    res.nodes[2 * r + 1] = NONE;
+  for (uint32_t r = R3; r < W.P0; ++r) {
+    nodes[2 * r] = LEAF | 0u;
+    nodes[2 * r + 1] = NONE;
   }
   if (next_node != nn || next_leaf != nl) return -4;
+  std::atomic<size_t> next{0};
+  std::vector<std::vector<uint64_t>> hists(std::max(1, nthreads), std::vector<uint64_t>(64, 0));
+  std::vector<uint32_t> mds(std::max(1, nthreads), 0);
+  std::atomic<int> bad{0};
+  auto work = [&](int t) {
+    for (;;) {
+      const size_t i = next.fetch_add(1);
+      if (i >= tasks.size()) break;
+      const Task& k = tasks[i];
+      const Pool<T>& P = W.subs[k.sub];
+      uint64_t nn_t = k.node_base, nl_t = k.leaf_base;
+      // the subtree root's own record: its group is the first of its range
+      nodes[2 * k.dst] = (uint32_t)nn_t;
+      const uint32_t c = P.child[0];
+      nn_t += 8;
+      for (uint32_t o = 0; o < 8; ++o)
+        emit_tree<T>(W, &P, c + o, k.node_base + o, (uint32_t)k.dst, k.d + 1, nodes, leaves, fmt,
+                     nn_t, nl_t, hists[t].data(), mds[t], false, [](int32_t, uint64_t, int) {});
+      if (nn_t != k.node_base + P.size() - 1 || nl_t != k.leaf_base + W.sub_leaves[k.sub])
+        bad = 1;
+    }
+  };
+  int nt = std::max(1, nthreads);
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& t : th) t.join();
+  if (bad) return -4;
+  for (int t = 0; t < nt; ++t) {
+    for (int j = 0; j < 64; ++j) hist[j] += hists[t][j];
+    md = std::max(md, mds[t]);
+  }
+  if (hist_out) std::memcpy(hist_out, hist.data(), 64 * 8);
+  if (md_out) *md_out = md;
   return 0;
 }
 
@@ -390,7 +486,9 @@ int build(uint32_t R, uint32_t D, double k, uint32_t S, int nthreads, const Stro
 
 extern "C" {
 
-// Builds a canvas.  Returns 0 and an opaque handle on success, < 0 on error.
+// Builds a canvas (paints every stroke into the trees).  Returns 0 and an
+// opaque handle on success, < 0 on error; cg_result_sizes then gives the
+// pool's size and cg_emit writes it.
 int cg_build(uint32_t R, uint32_t max_depth, double k_refine, uint32_t split_depth, int nthreads,
              int n_strokes, const int64_t* stamp_off, const double* stamps, const double* rgb,
              const double* sigma, const double* radius, int leaf_format, void** handle) {
@@ -400,12 +498,18 @@ int cg_build(uint32_t R, uint32_t max_depth, double k_refine, uint32_t split_dep
   Strokes st{n_strokes, stamp_off, (const Stamp*)stamps, rgb, sigma, radius};
   Result* res = new (std::nothrow) Result();
   if (!res) return -11;
+  res->fmt = leaf_format;
   int rc;
   try {
-    if (leaf_format == 1)
-      rc = build<double>(R, max_depth, k_refine, split_depth, nthreads, st, leaf_format, *res);
-    else
-      rc = build<float>(R, max_depth, k_refine, split_depth, nthreads, st, leaf_format, *res);
+    if (leaf_format == 1) {
+      res->pd = new Painted<double>();
+      rc = build<double>(R, max_depth, k_refine, split_depth, nthreads, st, *res->pd,
+                         res->n_nodes, res->n_leaves);
+    } else {
+      res->pf = new Painted<float>();
+      rc = build<float>(R, max_depth, k_refine, split_depth, nthreads, st, *res->pf,
+                        res->n_nodes, res->n_leaves);
+    }
   } catch (const std::bad_alloc&) {
     rc = -12;
   }
@@ -417,18 +521,27 @@ int cg_build(uint32_t R, uint32_t max_depth, double k_refine, uint32_t split_dep
   return 0;
 }
 
-void cg_result_sizes(void* h, uint64_t* n_nodes, uint64_t* n_leaves, uint32_t* max_depth_seen) {
+void cg_result_sizes(void* h, uint64_t* n_nodes, uint64_t* n_leaves) {
   Result* r = (Result*)h;
   *n_nodes = r->n_nodes;
   *n_leaves = r->n_leaves;
-  *max_depth_seen = r->max_depth_seen;
 }
 
-void cg_result_copy(void* h, uint32_t* nodes, void* leaves, uint64_t* depth_hist64) {
+// Writes the pool into the caller's arrays: nodes (2 uint32 per node), leaves
+// (8 or 32 bytes per leaf), leaves per depth (64 uint64) and the deepest
+// leaf depth.  Returns 0, or < 0 if the emission disagrees with the sizes.
+int cg_emit(void* h, uint32_t* nodes, void* leaves, uint64_t* depth_hist64,
+            uint32_t* max_depth_seen, int nthreads) {
   Result* r = (Result*)h;
-  if (nodes) std::memcpy(nodes, r->nodes.data(), r->nodes.size() * 4);
-  if (leaves) std::memcpy(leaves, r->leaves.data(), r->leaves.size());
-  if (depth_hist64) std::memcpy(depth_hist64, r->depth_hist.data(), 64 * 8);
+  try {
+    if (r->pd)
+      return emit<double>(*r->pd, r->n_nodes, r->n_leaves, nodes, (uint8_t*)leaves, r->fmt,
+                          depth_hist64, max_depth_seen, nthreads);
+    return emit<float>(*r->pf, r->n_nodes, r->n_leaves, nodes, (uint8_t*)leaves, r->fmt,
+                       depth_hist64, max_depth_seen, nthreads);
+  } catch (const std::bad_alloc&) {
+    return -12;
+  }
 }
 
 void cg_result_free(void* h) { delete (Result*)h; }

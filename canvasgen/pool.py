@@ -82,9 +82,9 @@ def _load():
         lib.cg_build.argtypes = [u32, u32, f64, u32, i32, i32, vp, vp, vp, vp, vp, i32,
                                  ctypes.POINTER(vp)]
         lib.cg_build.restype = i32
-        lib.cg_result_sizes.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64),
-                                        ctypes.POINTER(u32)]
-        lib.cg_result_copy.argtypes = [vp, vp, vp, vp]
+        lib.cg_result_sizes.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        lib.cg_emit.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u32), i32]
+        lib.cg_emit.restype = i32
         lib.cg_result_free.argtypes = [vp]
         lib.cg_set_verbose.argtypes = [i32]
         lib.cg_set_verbose.restype = None
@@ -115,11 +115,13 @@ def build_from_strokes(strokes, R: int, max_depth: int, k: float, leaf_format: i
         raise RuntimeError(f"canvas builder failed with code {rc}")
     try:
         nn, nl, md = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
-        lib.cg_result_sizes(h, ctypes.byref(nn), ctypes.byref(nl), ctypes.byref(md))
+        lib.cg_result_sizes(h, ctypes.byref(nn), ctypes.byref(nl))
         nodes = np.empty((nn.value, 2), np.uint32)
         leaves = np.empty(nl.value, LEAF_DTYPE[leaf_format])
         hist = np.zeros(64, np.uint64)
-        lib.cg_result_copy(h, ptr(nodes), ptr(leaves), ptr(hist))
+        rc = lib.cg_emit(h, ptr(nodes), ptr(leaves), ptr(hist), ctypes.byref(md), threads)
+        if rc != 0:
+            raise RuntimeError(f"canvas builder emission failed with code {rc}")
     finally:
         lib.cg_result_free(h)
     stats = dict(max_depth_seen=int(md.value), leaf_depth_hist=hist[:md.value + 1].tolist(),
