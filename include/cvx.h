@@ -152,6 +152,11 @@ typedef struct {
   uint32_t per_ray_start; /* 0: when a view's eye lies inside the canvas (off every cell
                             plane), its rays share the leaf holding the eye, located once
                             per view; 1: every ray locates its own first leaf (same result) */
+  uint32_t wide_offsets; /* 0: pools of at most 2^28 nodes are read with 32-bit byte offsets
+                            from the pool base, larger ones with 64-bit addresses; 1: every
+                            pool is read with 64-bit addresses, the code that pools above
+                            2^28 nodes always take (same result; for checking that code on
+                            any pool) */
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;
@@ -167,8 +172,12 @@ typedef struct {
 #define CVX_STAT_COUNT 8
 
 /* Create a context on HIP device `hip_device` that enqueues on `hip_stream`
- * (a hipStream_t, borrowed; NULL = the null stream).  Device memory is
- * allocated per uploaded pool and per render configuration. */
+ * (a hipStream_t, borrowed; NULL = the null stream).  The context owns the
+ * GPU-side pools of the canvases uploaded to it (the GPU memory layout of
+ * Sec. 4.1.2).  Device memory is allocated per uploaded pool and per render
+ * configuration.  Returns CVX_ERR_INVALID_ARG for a NULL ctx or a device
+ * index out of range, CVX_ERR_HIP if the runtime fails, CVX_ERR_OOM if the
+ * host allocation fails; *ctx is NULL on failure. */
 int cvx_create(cvx_ctx** ctx, int hip_device, void* hip_stream);
 
 /* Upload a canvas pool (Sec. 4.1.1-4.1.2): host arrays are read during the
@@ -187,10 +196,14 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
                     uint64_t n_leaves);
 
 /* Render n_views views into out_dev (a device buffer of at least
- * max(out_offset_px + W*H) RGBA pixels, float unless opts->out_f64).
- * Asynchronous on the context stream; the caller synchronises.  The views
- * array is copied before return.  Every pixel is computed by one lane in a
- * fixed order, so the output does not depend on scheduling or tuning. */
+ * max(out_offset_px + W*H) RGBA pixels, float unless opts->out_f64): one ray
+ * per pixel from the full-precision eye (Sec. 6.1), traversed leaf to leaf
+ * through the neighbour graph and composited front to back until the stop
+ * opacity or the canvas exit (Sec. 6.2).  Asynchronous on the context
+ * stream; the caller synchronises.  The views array is copied before return.
+ * Every pixel is computed by one lane in a fixed order, so the output does
+ * not depend on scheduling or tuning.  Returns CVX_ERR_INVALID_ARG for bad
+ * options or views (nothing is launched), CVX_ERR_HIP if a launch fails. */
 int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
                const cvx_render_opts* opts);
 
@@ -327,10 +340,13 @@ int cvx_stroke_begin(cvx_ctx* ctx, int canvas_id, const cvx_stroke* stroke, cons
  * possibly not yet painted. */
 int cvx_stroke_step(cvx_ctx* ctx, int canvas_id, uint64_t* pending);
 
-/* Release the pool under canvas_id (CVX_ERR_NOT_FOUND if none). */
+/* Release the GPU pool (Sec. 4.1.2) under canvas_id after the context's
+ * stream has drained (CVX_ERR_NOT_FOUND if none, CVX_ERR_INVALID_ARG for an
+ * id out of range). */
 int cvx_free_pool(cvx_ctx* ctx, int canvas_id);
 
-/* Release everything owned by the context (waits for its stream). */
+/* Release everything owned by the context, the GPU pools of Sec. 4.1.2
+ * included (waits for its stream first).  NULL is ignored. */
 void cvx_destroy(cvx_ctx* ctx);
 
 /* Message of the last failed call on ctx ("" if none); valid until the next call. */

@@ -297,25 +297,34 @@ int cvx_pool_bytes(cvx_ctx* ctx, int canvas_id, uint64_t* bytes) {
   return CVX_OK;
 }
 
-int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
-               const cvx_render_opts* opts) {
-  if (!ctx) return CVX_ERR_INVALID_ARG;
-  ctx->err.clear();
-  cvx_render_opts o{};
-  if (opts) o = *opts;
+}  // extern "C"
+
+namespace {
+
+// Launch shape and mode of one render call, from its options.
+struct RenderPlan {
+  uint32_t tw = 8, th = 8, wg = 256, wgs = 0;
+};
+
+// Checks the options and views of a render call (nothing is launched on an
+// error).
+int render_check(cvx_ctx* ctx, const cvx_view* views, int n_views, const void* out_dev,
+                 const cvx_render_opts& o, RenderPlan& p) {
   if (o.variant > CVX_VARIANT_FP16_CELL_LOCAL)
     return fail(ctx, CVX_ERR_INVALID_ARG, "unknown variant");
-  uint32_t tw = o.tile_w ? o.tile_w : 8, th = o.tile_h ? o.tile_h : 8;
-  if (tw * th != 64 || tw == 0 || th == 0)
+  p.tw = o.tile_w ? o.tile_w : 8;
+  p.th = o.tile_h ? o.tile_h : 8;
+  if (p.tw * p.th != 64 || p.tw == 0 || p.th == 0)
     return fail(ctx, CVX_ERR_INVALID_ARG, "tile_w * tile_h must be 64");
-  uint32_t wg = o.wg_size ? o.wg_size : 256;
-  if (wg != 64 && wg != 128 && wg != 256)
+  p.wg = o.wg_size ? o.wg_size : 256;
+  if (p.wg != 64 && p.wg != 128 && p.wg != 256)
     return fail(ctx, CVX_ERR_INVALID_ARG, "wg_size must be 64, 128 or 256");
-  uint32_t wgs = o.workgroups ? o.workgroups : (uint32_t)ctx->n_cu * (2048u / wg);
-  if (wgs > (1u << 20)) return fail(ctx, CVX_ERR_INVALID_ARG, "too many workgroups");
+  p.wgs = o.workgroups ? o.workgroups : (uint32_t)ctx->n_cu * (2048u / p.wg);
+  if (p.wgs > (1u << 20)) return fail(ctx, CVX_ERR_INVALID_ARG, "too many workgroups");
   if (o.top_lookup > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "top_lookup must be 0 or 1");
   if (o.single_queue > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "single_queue must be 0 or 1");
   if (o.per_ray_start > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "per_ray_start must be 0 or 1");
+  if (o.wide_offsets > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "wide_offsets must be 0 or 1");
   if (o.out_f64 && o.variant != CVX_VARIANT_FP64_PLAIN)
     return fail(ctx, CVX_ERR_INVALID_ARG, "out_f64 needs the FP64_PLAIN variant");
   const cvx_trace* tr = o.trace;
@@ -341,6 +350,164 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
       return fail(ctx, CVX_ERR_INVALID_ARG,
                   "view " + std::to_string(i) + ": FP32 variants read RGBA8_F16 leaves only");
   }
+  return CVX_OK;
+}
+
+// Where a render call stages its view table and header: host copies (pinned)
+// and their device destinations.  With `contiguous`, h_views follows h_hdr
+// and d_views follows d_hdr, and one copy moves both.
+struct RenderStage {
+  DView* h_views;
+  CastHeader* h_hdr;
+  DView* d_views;
+  CastHeader* d_hdr;
+  hipEvent_t staged;  // recorded after the copies; the host staging is reused only after it
+  bool* staged_pending;
+  bool contiguous;
+};
+
+// Fills the staged views and header, copies them to the device and launches
+// the view-start, queue-reset and cast kernels, eagerly or through the
+// context's graph.
+int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+                  const cvx_render_opts& o, const RenderPlan& p, const RenderStage& st) {
+  const cvx_trace* tr = o.trace;
+  uint64_t first = 0;
+  for (int i = 0; i < n_views; ++i) {
+    const cvx_view& v = views[i];
+    const DevCanvas& c = ctx->canvases[v.canvas_id];
+    DView& dv = st.h_views[i];
+    std::memset(&dv, 0, sizeof(dv));
+    dv.rec = c.rec;
+    dv.pay = c.pay;
+    dv.R = c.desc.R;
+    dv.fmt = c.desc.leaf_format;
+    dv.max_depth = c.depth;
+    for (int k = 0; k < 3; ++k) {
+      dv.o[k] = (v.eye[k] - c.desc.origin[k]) / c.desc.root_edge;
+      dv.right[k] = v.right[k];
+      dv.up[k] = v.up[k];
+      dv.fwd[k] = v.fwd[k];
+    }
+    dv.tan_x = v.tan_half_fov_x;
+    dv.tan_y = v.tan_half_fov_y;
+    dv.W = v.W;
+    dv.H = v.H;
+    dv.out_off = v.out_offset_px;
+    dv.alpha_stop = v.alpha_stop;
+    dv.tiles_x = (v.W + p.tw - 1) / p.tw;
+    uint64_t tiles_y = (v.H + p.th - 1) / p.th;
+    dv.first_tile = first;
+    first += (uint64_t)dv.tiles_x * tiles_y;
+    uint64_t cap = 3ull * c.desc.R * (1ull << std::min<uint32_t>(c.depth, 40)) + 16;
+    dv.max_steps = (uint32_t)std::min<uint64_t>(cap, 1ull << 22);
+    dv.n_nodes = (uint32_t)c.n_nodes;
+    const bool top = o.top_lookup == 0 && c.top_depth > 0;
+    dv.top_depth = top ? c.top_depth : 0;
+    dv.top = top ? c.top : nullptr;
+    dv.start_ok = 0;  // set on the device by k_view_starts
+  }
+  CastHeader& H = *st.h_hdr;
+  H.total_work = tr ? (tr->n + 63) / 64 : first;
+  H.n_rays = tr ? tr->n : 0;
+  H.n_views = (uint32_t)n_views;
+  H.n_queues = o.single_queue ? 1u : cvx::CVX_NQ;
+  for (auto& q : H.queue) q.next = 0;
+  if (H.total_work >= (1ull << 32)) return fail(ctx, CVX_ERR_INVALID_ARG, "too much work in one call");
+  if (st.contiguous) {
+    CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader) + sizeof(DView) * n_views,
+                           hipMemcpyHostToDevice, ctx->stream));
+  } else {
+    CVX_HIP(hipMemcpyAsync(st.d_views, st.h_views, sizeof(DView) * n_views,
+                           hipMemcpyHostToDevice, ctx->stream));
+    CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader), hipMemcpyHostToDevice,
+                           ctx->stream));
+  }
+  CVX_HIP(hipEventRecord(st.staged, ctx->stream));
+  *st.staged_pending = true;
+
+  CastArgs a{};
+  a.views = st.d_views;
+  a.hdr = st.d_hdr;
+  a.out = out_dev;
+  a.stats = o.stats;
+  a.tile_w = p.tw;
+  a.tile_h = p.th;
+  a.small_pools = o.wide_offsets ? 0u : 1u;
+  for (int i = 0; i < n_views; ++i)
+    if (ctx->canvases[views[i].canvas_id].n_nodes > (1ull << 28)) a.small_pools = 0;
+  if (tr) {
+    a.ray_ids = tr->ray_ids;
+    a.max_leaves = tr->max_leaves;
+    a.leaf_ids = tr->leaf_ids;
+    a.local_len = tr->local_len;
+    a.local_len64 = tr->local_len64;
+    a.n_leaves = tr->n_leaves;
+    a.flags = tr->flags;
+    a.trace_rgba = tr->rgba;
+    a.end_point = tr->end_point;
+  }
+  const bool stats = o.stats != nullptr;
+  const uint32_t shared_start = o.per_ray_start ? 0u : 1u;
+  if (!o.use_graph || tr) {
+    int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
+    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_view_starts");
+    le = cvx::launch_reset(ctx->stream, st.d_hdr);
+    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_reset");
+    le = cvx::launch_cast(ctx->stream, o.variant, tr != nullptr, stats, o.out_f64 != 0, a, p.wgs,
+                          p.wg);
+    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_cast");
+    return CVX_OK;
+  }
+  GraphKey key;
+  key.variant = o.variant;
+  key.tw = p.tw;
+  key.th = p.th;
+  key.wgs = p.wgs;
+  key.wg = p.wg;
+  key.trace = false;
+  key.stats = stats;
+  key.out64 = o.out_f64 != 0;
+  key.small = a.small_pools != 0;
+  key.per_ray_start = o.per_ray_start != 0;
+  key.out = out_dev;
+  key.stats_ptr = o.stats;
+  key.views = st.d_views;
+  if (!ctx->gexec || !(key == ctx->gkey)) {
+    drop_graph(ctx);
+    CVX_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
+    if (le == hipSuccess) le = cvx::launch_reset(ctx->stream, st.d_hdr);
+    if (le == hipSuccess)
+      le = cvx::launch_cast(ctx->stream, o.variant, false, stats, o.out_f64 != 0, a, p.wgs, p.wg);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(ctx, (hipError_t)le, "graph capture launch");
+    }
+    if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
+    ctx->graph = g;
+    CVX_HIP(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+    ctx->gkey = key;
+  }
+  CVX_HIP(hipGraphLaunch(ctx->gexec, ctx->stream));
+  return CVX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+               const cvx_render_opts* opts) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  cvx_render_opts o{};
+  if (opts) o = *opts;
+  RenderPlan p;
+  int rc = render_check(ctx, views, n_views, out_dev, o, p);
+  if (rc) return rc;
 
   CVX_HIP(hipSetDevice(ctx->device));
   if (ctx->staged_pending) {
@@ -364,121 +531,9 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     ctx->views_cap = cap;
     drop_graph(ctx);
   }
-  uint64_t first = 0;
-  for (int i = 0; i < n_views; ++i) {
-    const cvx_view& v = views[i];
-    const DevCanvas& c = ctx->canvases[v.canvas_id];
-    DView& dv = ctx->h_views[i];
-    std::memset(&dv, 0, sizeof(dv));
-    dv.rec = c.rec;
-    dv.pay = c.pay;
-    dv.R = c.desc.R;
-    dv.fmt = c.desc.leaf_format;
-    dv.max_depth = c.depth;
-    for (int k = 0; k < 3; ++k) {
-      dv.o[k] = (v.eye[k] - c.desc.origin[k]) / c.desc.root_edge;
-      dv.right[k] = v.right[k];
-      dv.up[k] = v.up[k];
-      dv.fwd[k] = v.fwd[k];
-    }
-    dv.tan_x = v.tan_half_fov_x;
-    dv.tan_y = v.tan_half_fov_y;
-    dv.W = v.W;
-    dv.H = v.H;
-    dv.out_off = v.out_offset_px;
-    dv.alpha_stop = v.alpha_stop;
-    dv.tiles_x = (v.W + tw - 1) / tw;
-    uint64_t tiles_y = (v.H + th - 1) / th;
-    dv.first_tile = first;
-    first += (uint64_t)dv.tiles_x * tiles_y;
-    uint64_t cap = 3ull * c.desc.R * (1ull << std::min<uint32_t>(c.depth, 40)) + 16;
-    dv.max_steps = (uint32_t)std::min<uint64_t>(cap, 1ull << 22);
-    dv.n_nodes = (uint32_t)c.n_nodes;
-    const bool top = o.top_lookup == 0 && c.top_depth > 0;
-    dv.top_depth = top ? c.top_depth : 0;
-    dv.top = top ? c.top : nullptr;
-    dv.start_ok = 0;  // set on the device by k_view_starts
-  }
-  CastHeader& H = *ctx->h_hdr;
-  H.total_work = tr ? (tr->n + 63) / 64 : first;
-  H.n_rays = tr ? tr->n : 0;
-  H.n_views = (uint32_t)n_views;
-  H.n_queues = o.single_queue ? 1u : cvx::CVX_NQ;
-  for (auto& q : H.queue) q.next = 0;
-  if (H.total_work >= (1ull << 32)) return fail(ctx, CVX_ERR_INVALID_ARG, "too much work in one call");
-  CVX_HIP(hipMemcpyAsync(ctx->d_views, ctx->h_views, sizeof(DView) * n_views,
-                         hipMemcpyHostToDevice, ctx->stream));
-  CVX_HIP(hipMemcpyAsync(ctx->d_hdr, ctx->h_hdr, sizeof(CastHeader), hipMemcpyHostToDevice,
-                         ctx->stream));
-  CVX_HIP(hipEventRecord(ctx->staged, ctx->stream));
-  ctx->staged_pending = true;
-
-  CastArgs a{};
-  a.views = ctx->d_views;
-  a.hdr = ctx->d_hdr;
-  a.out = out_dev;
-  a.stats = o.stats;
-  a.tile_w = tw;
-  a.tile_h = th;
-  a.small_pools = 1;
-  for (int i = 0; i < n_views; ++i)
-    if (ctx->canvases[views[i].canvas_id].n_nodes > (1ull << 28)) a.small_pools = 0;
-  if (tr) {
-    a.ray_ids = tr->ray_ids;
-    a.max_leaves = tr->max_leaves;
-    a.leaf_ids = tr->leaf_ids;
-    a.local_len = tr->local_len;
-    a.local_len64 = tr->local_len64;
-    a.n_leaves = tr->n_leaves;
-    a.flags = tr->flags;
-    a.trace_rgba = tr->rgba;
-    a.end_point = tr->end_point;
-  }
-  const bool stats = o.stats != nullptr;
-  const uint32_t shared_start = o.per_ray_start ? 0u : 1u;
-  if (!o.use_graph || tr) {
-    int le = cvx::launch_view_starts(ctx->stream, ctx->d_views, ctx->d_hdr, shared_start);
-    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_view_starts");
-    le = cvx::launch_reset(ctx->stream, ctx->d_hdr);
-    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_reset");
-    le = cvx::launch_cast(ctx->stream, o.variant, tr != nullptr, stats, o.out_f64 != 0, a, wgs, wg);
-    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_cast");
-    return CVX_OK;
-  }
-  GraphKey key;
-  key.variant = o.variant;
-  key.tw = tw;
-  key.th = th;
-  key.wgs = wgs;
-  key.wg = wg;
-  key.trace = false;
-  key.stats = stats;
-  key.out64 = o.out_f64 != 0;
-  key.small = a.small_pools != 0;
-  key.per_ray_start = o.per_ray_start != 0;
-  key.out = out_dev;
-  key.stats_ptr = o.stats;
-  key.views = ctx->d_views;
-  if (!ctx->gexec || !(key == ctx->gkey)) {
-    drop_graph(ctx);
-    CVX_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    int le = cvx::launch_view_starts(ctx->stream, ctx->d_views, ctx->d_hdr, shared_start);
-    if (le == hipSuccess) le = cvx::launch_reset(ctx->stream, ctx->d_hdr);
-    if (le == hipSuccess)
-      le = cvx::launch_cast(ctx->stream, o.variant, false, stats, o.out_f64 != 0, a, wgs, wg);
-    hipGraph_t g = nullptr;
-    hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
-    if (le != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return hip_fail(ctx, (hipError_t)le, "graph capture launch");
-    }
-    if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
-    ctx->graph = g;
-    CVX_HIP(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
-    ctx->gkey = key;
-  }
-  CVX_HIP(hipGraphLaunch(ctx->gexec, ctx->stream));
-  return CVX_OK;
+  const RenderStage st{ctx->h_views, ctx->h_hdr,  ctx->d_views,           ctx->d_hdr,
+                       ctx->staged,  &ctx->staged_pending, false};
+  return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 
 int cvx_pool_nodes(cvx_ctx* ctx, int canvas_id, uint64_t* n_nodes) {

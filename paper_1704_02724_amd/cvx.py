@@ -97,6 +97,7 @@ class cvx_render_opts(ctypes.Structure):
                 ("wg_size", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
                 ("out_f64", ctypes.c_uint32), ("top_lookup", ctypes.c_uint32),
                 ("single_queue", ctypes.c_uint32), ("per_ray_start", ctypes.c_uint32),
+                ("wide_offsets", ctypes.c_uint32),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
@@ -346,8 +347,9 @@ def cvx_validate_views(views, descs):
 
 def make_opts(variant="fp32_rebased", tile=(0, 0), workgroups=0, wg_size=0, use_graph=False,
               out_f64=False, trace=None, stats_ptr=0, top_lookup=0, single_queue=0,
-              per_ray_start=0):
+              per_ray_start=0, wide_offsets=0):
     o = cvx_render_opts()
+    o.wide_offsets = int(wide_offsets)
     o.top_lookup = int(top_lookup)
     o.single_queue = int(single_queue)
     o.per_ray_start = int(per_ray_start)

@@ -296,6 +296,55 @@ def test_error_paths(sess):
     assert e.value.code == cvx.CVX_ERR_NOT_FOUND
 
 
+def test_upload_oom_keeps_the_old_pool(sess):
+    """cvx_upload_pool checks the device room a pool needs before allocating
+    anything: with the device nearly full it returns CVX_ERR_OOM and the
+    pool already under that canvas id renders as before."""
+    from paper_1704_02724_amd import cvx
+    torch = sess.torch
+    cv = trees.random_tree(1, 4, seed=51, leaf_format=LEAF_RGBA8_F16)
+    sess.upload(5, cv)
+    v = [make_view((0.5, 0.5, -1.0), (0.0, 0.0, 1.0), 0.5, 16, 16, canvas_id=5)]
+    out = torch.zeros((256, 4), dtype=torch.float32, device=sess.device)
+    ref = sess.render(v, out=out).cpu().numpy()
+    big = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=8, H=8).canvases[0]
+    need = 40 * big.n_nodes + 8 * len(big.leaves)  # the upload's own estimate, roughly
+    keep = (64 << 20) + need // 4                  # below need + the 64 MiB margin
+    torch.cuda.synchronize()
+    fill = []
+    try:
+        while True:
+            free, _ = torch.cuda.mem_get_info(sess.device)
+            if free <= keep + (2 << 20):
+                break
+            chunk = min(free - keep, 16 << 30)
+            fill.append(torch.empty(chunk, dtype=torch.uint8, device=sess.device))
+        with pytest.raises(cvx.CvxError) as e:
+            sess.upload(5, big)
+        assert e.value.code == cvx.CVX_ERR_OOM
+        assert "device bytes" in str(e.value)
+    finally:
+        del fill
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    np.testing.assert_array_equal(sess.render(v, out=out).cpu().numpy(), ref)
+
+
+def test_wide_offsets_same_image(sess):
+    """Pools of at most 2^28 nodes are read with 32-bit offsets unless
+    wide_offsets asks for the 64-bit addressing that larger pools take; the
+    images are the same in every tuned launch shape."""
+    w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=120, H=90)
+    sess.upload(0, w.canvases[0])
+    for kw in (dict(), dict(tile=(16, 4), wg_size=64, top_lookup=1),
+               dict(tile=(4, 16), wg_size=128, single_queue=1, per_ray_start=1)):
+        ref = sess.render(w.views, "fp32_rebased", **kw).cpu().numpy()
+        img = sess.render(w.views, "fp32_rebased", wide_offsets=1, **kw).cpu().numpy()
+        np.testing.assert_array_equal(img, ref)
+        img = sess.render(w.views, "fp32_rebased", wide_offsets=1, use_graph=True, **kw)
+        np.testing.assert_array_equal(img.cpu().numpy(), ref)
+
+
 def test_autotune_picks_a_timed_shape_and_keeps_the_image(sess):
     """cvx_autotune times every candidate launch shape; every candidate renders
     the same image, and the one it returns is the fastest it timed."""

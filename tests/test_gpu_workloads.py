@@ -39,6 +39,12 @@ def depth30():
 
 
 def _sampled(sess, w, ids, variant):
+    """Leaf sequences of the trace kernel against the oracle, and RGBA of the
+    image rendered as the benchmark times it (autotuned launch shape, graph
+    replay) against the oracle.  The two kernel instances are tied together:
+    the rendered pixels equal the traced RGBA bit for bit, and the image of
+    the instance that reads pools with 64-bit addresses (the one pools above
+    2^28 nodes take) equals the default one bit for bit."""
     for i, c in enumerate(w.canvases):
         sess.upload(i, c)
     orc = oracle.render(w.canvases, w.views, ids, max_leaves=ML)
@@ -51,6 +57,9 @@ def _sampled(sess, w, ids, variant):
     px = (ids & np.uint64(0xFFFFFFFF)).astype(np.int64)
     offs = np.array([v["out_offset_px"] for v in w.views], np.int64)
     err = rgba_err(img[offs[vi] + px], orc["rgba"], cmp["ok_mask"])
+    np.testing.assert_array_equal(gpu["rgba"], img[offs[vi] + px])
+    wide = sess.render(w.views, variant, use_graph=True, wide_offsets=1, **tuning)
+    np.testing.assert_array_equal(wide.cpu().numpy(), img)
     return cmp, err, orc, gpu
 
 
@@ -72,6 +81,24 @@ def test_depth24_sub_resolution_clip(sess, depth24):
     cmp, err, orc, gpu = _sampled(sess, depth24, ids, "fp32_rebased")
     assert orc["flags"][0] == 0
     assert cmp["seq_mismatch"] == 0, (orc["n_leaves"], gpu["n_leaves"])
+
+
+def test_depth24_k10_sampled(sess):
+    """The depth-24 strokes with refine factor 10: leaves reach depth 24 and
+    the pool has 661 M nodes, above the 2^28 nodes up to which pools are read
+    with 32-bit offsets, so the image comes from the 64-bit-address render
+    kernel on its production path (the one the large canvas takes)."""
+    w = configs.depth24(k=10.0)
+    assert int(w.canvases[0].max_depth) == 24
+    assert w.canvases[0].n_nodes > 2 ** 28
+    ids = sample_ray_ids(w.views, 32768, 2410)
+    cmp, err, orc, _ = _sampled(sess, w, ids, "fp32_rebased")
+    print(f"depth24 k=10: {cmp['n']} rays, flagged {cmp['flagged']}, "
+          f"mismatch {cmp['seq_mismatch']}, rgba err {err:.3g}, "
+          f"mean leaves {orc['n_leaves'].mean():.1f}, nodes {w.canvases[0].n_nodes}")
+    assert cmp["n"] - cmp["flagged"] >= 16384
+    assert cmp["seq_mismatch"] == 0, cmp
+    assert err <= 1e-3
 
 
 @pytest.mark.parametrize("variant", ["fp32_rebased", "fp64_plain"])
