@@ -207,6 +207,22 @@ int cvx_upload_pool(cvx_ctx* ctx, int canvas_id, const cvx_canvas_desc* desc,
 int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
                const cvx_render_opts* opts);
 
+/* Allocation-free rendering, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same as cvx_render with the same arguments and the same
+ * result, except that the per-call view table and work-queue header live in
+ * a fixed device array of the library (one per GPU, held until the process
+ * ends) instead of memory the context allocates: the call makes no
+ * hipMalloc, hipFree or other allocation.  n_views is limited to
+ * CVX_NOALLOC_MAX_VIEWS (CVX_ERR_INVALID_ARG beyond it, nothing launched) and
+ * opts->use_graph must be 0 (instantiating a graph allocates).  Every call on
+ * one GPU shares that GPU's array, whatever the context: calls that overlap
+ * on one GPU (from two streams or two contexts) race and are not allowed;
+ * calls on one context's stream are ordered and safe. */
+#define CVX_NOALLOC_MAX_VIEWS 256
+int cvx_render_noalloc(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+                       const cvx_render_opts* opts);
+
 /* One candidate launch shape timed by cvx_autotune. */
 typedef struct {
   uint32_t tile_w, tile_h; /* pixel tile, tile_w * tile_h = 64 */

@@ -46,6 +46,12 @@ struct cvx_ctx {
   CastHeader* h_hdr = nullptr;  // pinned staging
   hipEvent_t staged{};
   bool staged_pending = false;
+  // cvx_render_noalloc: the library's device scratch array on this device
+  // (a CastHeader, then the view table) and a pinned host copy of it
+  void* d_scratch = nullptr;
+  void* h_scratch = nullptr;
+  hipEvent_t scratch_staged{};
+  bool scratch_pending = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey;
@@ -154,6 +160,12 @@ int cvx_create(cvx_ctx** out, int hip_device, void* hip_stream) {
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_hdr, sizeof(CastHeader));
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_hdr, sizeof(CastHeader), 0);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
+  // the allocation-free render path: the address of this device's scratch
+  // array (looked up once per device, with the device current) and the
+  // pinned host copy its calls stage through
+  if (e == hipSuccess) e = (hipError_t)cvx::scratch_address(hip_device, &ctx->d_scratch);
+  if (e == hipSuccess) e = hipHostMalloc(&ctx->h_scratch, cvx::CVX_SCRATCH_BYTES, 0);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->scratch_staged, hipEventDisableTiming);
   if (e != hipSuccess) {
     cvx_destroy(ctx);
     return CVX_ERR_HIP;
@@ -173,6 +185,8 @@ void cvx_destroy(cvx_ctx* ctx) {
   if (ctx->h_views) (void)hipHostFree(ctx->h_views);
   if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
   if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+  if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
+  if (ctx->scratch_staged) (void)hipEventDestroy(ctx->scratch_staged);
   delete ctx;
 }
 
@@ -533,6 +547,38 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   }
   const RenderStage st{ctx->h_views, ctx->h_hdr,  ctx->d_views,           ctx->d_hdr,
                        ctx->staged,  &ctx->staged_pending, false};
+  return render_launch(ctx, views, n_views, out_dev, o, p, st);
+}
+
+int cvx_render_noalloc(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
+                       const cvx_render_opts* opts) {
+  if (!ctx) return CVX_ERR_INVALID_ARG;
+  ctx->err.clear();
+  cvx_render_opts o{};
+  if (opts) o = *opts;
+  if (n_views > CVX_NOALLOC_MAX_VIEWS)
+    return fail(ctx, CVX_ERR_INVALID_ARG,
+                "n_views " + std::to_string(n_views) + " exceeds CVX_NOALLOC_MAX_VIEWS (" +
+                    std::to_string(CVX_NOALLOC_MAX_VIEWS) + ")");
+  if (o.use_graph)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "cvx_render_noalloc takes no graph (use_graph = 0)");
+  RenderPlan p;
+  int rc = render_check(ctx, views, n_views, out_dev, o, p);
+  if (rc) return rc;
+  if (!ctx->d_scratch || !ctx->h_scratch)
+    return fail(ctx, CVX_ERR_HIP, "the device scratch array was not found at cvx_create");
+  CVX_HIP(hipSetDevice(ctx->device));
+  // the previous call's copy out of the host staging must be done
+  if (ctx->scratch_pending) {
+    CVX_HIP(hipEventSynchronize(ctx->scratch_staged));
+    ctx->scratch_pending = false;
+  }
+  uint8_t* h = (uint8_t*)ctx->h_scratch;
+  uint8_t* d = (uint8_t*)ctx->d_scratch;
+  const RenderStage st{(DView*)(h + sizeof(CastHeader)), (CastHeader*)h,
+                       (DView*)(d + sizeof(CastHeader)), (CastHeader*)d,
+                       ctx->scratch_staged,              &ctx->scratch_pending,
+                       true};
   return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 

@@ -27,6 +27,8 @@
 //                end of Sec. 6.3 argues would suffice.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "cvx_internal.h"
 
 #ifndef CVX_CAST32_WAVES
@@ -1256,6 +1258,30 @@ int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32
 int launch_reset(void* stream, CastHeader* hdr) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, hdr);
   return (int)hipGetLastError();
+}
+
+// Device memory of cvx_render_noalloc: the call's CastHeader, then its view
+// table (CVX_NOALLOC_MAX_VIEWS records).  Each GPU holds its own copy for
+// the life of the process.  Host code never passes this name to a kernel or
+// a copy: the address on a device comes from scratch_address.
+static __device__ __align__(256) unsigned char scratch[CVX_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+
+int scratch_address(int device, void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxScratchDevices] = {};
+  if (device < 0 || device >= kMaxScratchDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return (int)hipSuccess;
 }
 
 }  // namespace cvx

@@ -178,6 +178,12 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
 int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out_f64,
                 const CastArgs& a, uint32_t workgroups, uint32_t wg_size);
 int launch_reset(void* stream, CastHeader* hdr);
+// Scratch of the allocation-free render entry point: a CastHeader followed by
+// CVX_NOALLOC_MAX_VIEWS view records, in a fixed device array of
+// cvx_cast.hip.  scratch_address returns its address on the current device
+// (looked up once per device; call with that device current).
+constexpr size_t CVX_SCRATCH_BYTES = sizeof(CastHeader) + CVX_NOALLOC_MAX_VIEWS * sizeof(DView);
+int scratch_address(int device, void** ptr);
 // the shared first leaf of every view whose eye lies inside its canvas
 int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable);
 // one level of a stroke's walk (cvx_stroke.hip); items == nullptr: the roots;

@@ -40,6 +40,7 @@ VARIANTS = {"fp32_rebased": 0, "fp64_plain": 1, "fp32_naive": 2, "fp32_cell_loca
 CVX_MAX_CANVASES = 64
 CVX_MAX_DEPTH = 30
 CVX_MAX_VIEWS = 4096
+CVX_NOALLOC_MAX_VIEWS = 256
 
 CVX_RAYFLAG_STEP_CAP = 1
 CVX_RAYFLAG_FP64_EXIT = 2
@@ -53,7 +54,8 @@ CVX_STAT_COUNT = 8
 EXPORTED = ["cvx_create", "cvx_upload_pool", "cvx_render", "cvx_free_pool", "cvx_destroy",
             "cvx_last_error", "cvx_status_str", "cvx_validate_pool", "cvx_validate_views",
             "cvx_pool_bytes", "cvx_autotune", "cvx_edit_pool", "cvx_pool_nodes",
-            "cvx_read_records", "cvx_read_payloads", "cvx_stroke_begin", "cvx_stroke_step"]
+            "cvx_read_records", "cvx_read_payloads", "cvx_stroke_begin", "cvx_stroke_step",
+            "cvx_render_noalloc"]
 
 CVX_EDIT_PAINT = 0
 CVX_EDIT_REFINE = 1
@@ -132,6 +134,8 @@ _lib.cvx_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp]
 _lib.cvx_upload_pool.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(cvx_canvas_desc), _vp,
                                  ctypes.c_uint64, _vp, ctypes.c_uint64]
 _lib.cvx_render.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(cvx_render_opts)]
+_lib.cvx_render_noalloc.argtypes = [_vp, _vp, ctypes.c_int, _vp,
+                                    ctypes.POINTER(cvx_render_opts)]
 _lib.cvx_free_pool.argtypes = [_vp, ctypes.c_int]
 _lib.cvx_destroy.argtypes = [_vp]
 _lib.cvx_destroy.restype = None
@@ -219,6 +223,14 @@ def cvx_render(ctx, views, out_ptr, opts=None):
     o = opts if opts is not None else cvx_render_opts()
     _check(ctx, _lib.cvx_render(ctx, ctypes.cast(views, _vp), len(views), _vp(int(out_ptr)),
                                 ctypes.byref(o)))
+
+
+def cvx_render_noalloc(ctx, views, out_ptr, opts=None):
+    """The allocation-free render: same arguments and result as cvx_render,
+    at most CVX_NOALLOC_MAX_VIEWS views, no graph."""
+    o = opts if opts is not None else cvx_render_opts()
+    _check(ctx, _lib.cvx_render_noalloc(ctx, ctypes.cast(views, _vp), len(views),
+                                        _vp(int(out_ptr)), ctypes.byref(o)))
 
 
 def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):

@@ -79,7 +79,9 @@ class Session:
         return max(v["out_offset_px"] + v["W"] * v["H"] for v in views)
 
     def render(self, views, variant="fp32_rebased", out=None, out_f64=False, stats=None,
-               **tuning):
+               noalloc=False, **tuning):
+        """cvx_render (or, with noalloc, cvx_render_noalloc) into `out`, a new
+        tensor when None."""
         torch = self.torch
         n_px = self.out_pixels(views)
         if out is None:
@@ -89,7 +91,8 @@ class Session:
         opts = cvx.make_opts(variant, out_f64=out_f64,
                              stats_ptr=stats.data_ptr() if stats is not None else 0, **tuning)
         self._enter()
-        cvx.cvx_render(self.ctx, varr, out.data_ptr(), opts)
+        (cvx.cvx_render_noalloc if noalloc else cvx.cvx_render)(self.ctx, varr, out.data_ptr(),
+                                                                 opts)
         self._leave(out, *([stats] if stats is not None else []))
         return out
 
