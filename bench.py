@@ -1,25 +1,31 @@
 """Benchmark: Mrays/s of the FP32-rebased deep-octree ray caster on one MI355X.
 
-Workload (default "depth24"): a unit-cube canvas refined to depth 22-24 by
-2,000 seeded strokes (radius 2^-20..2^-3, ~56 M nodes), rendered as a stereo
-pair of 1920x1080 views (90 deg FOV) from an eye placed just outside a small
-stroke.  One step = one cvx_render call over both views (a replayed HIP
-graph), with the pool already resident in HBM.
+Headline workload (default "large"): a unit-cube canvas refined to depth 26
+by 55,000 seeded strokes (radius 2^-24..2^-2, 1.46 G nodes, 35 GB of node
+records and payloads in HBM), rendered as a stereo pair of 2160x2160 views
+from an eye just outside a small stroke, rays stopping once their opacity
+reaches 0.99.  One step = one cvx_render call over both views (a replayed HIP
+graph, one persistent launch), with the pool already resident in HBM.
 
-The line also carries:
+The line also carries, for the headline workload:
   * the FP64-plain GPU caster timed on the same views,
   * parity against the CPU FP64 oracle on a seeded ray sample (leaf
-    sequences bit-exact outside 1e-12 face bands, RGBA <= 1e-3),
-  * the roofline of the cast kernel: algorithmic bytes per launch
-    (16 B per pixel + 8 B per leaf payload + 4 B per neighbour link or level
-    descended, counted by the kernel) over its event-timed duration, against
-    8 TB/s,
-  * the CPU oracle timed on the host cores over the whole workload, or over a
-    bounded seeded sample of it when it has more than 2^23 rays.
+    sequences bit-exact outside 1e-12 face bands, RGBA <= 1e-3); `value` is
+    null when parity fails,
+  * the naive canvas-global FP32 caster on the same sample (its leaf-sequence
+    mismatch rate and RGBA error: the precision failure the rebase removes),
+  * the roofline of the cast kernel: the bound the committed rocprofv3
+    counters show (vector instruction issue), the kernel's issue rate against
+    the chip's, and its algorithmic and measured HBM bytes against 8 TB/s,
+  * the CPU oracle timed on the host cores over a bounded seeded sample,
+and under "configs" the same measurements (fewer steps, no CPU leg) for the
+other workloads: the depth-24 stereo pair, the depth-30 zoomed view and the
+batch of 64 views over 8 canvases.
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -31,6 +37,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E
+N_SIMD = 1024      # 256 compute units x 4 SIMDs
+CLOCK = 2.4e9      # peak engine clock, Hz
+# Peak wave64 vector-instruction issue per SIMD per cycle: a SIMD executes a
+# 32-bit vector instruction of a wave64 over 64 lanes at 32 lanes per clock
+# (the non-packed FP32 rate behind the 157.3 TFLOP/s peak: 256 CUs x 4 SIMDs
+# x 32 lanes x 2 flops x 2.4 GHz), so at most one instruction every two
+# clocks.
+VALU_ISSUE_PER_SIMD_CYCLE = 0.5
+VALU_PEAK = N_SIMD * CLOCK * VALU_ISSUE_PER_SIMD_CYCLE  # wave64 instructions/s
+
+WORKLOADS = ("tiny", "depth24", "depth24_k10", "depth30", "depth30_k10", "batch", "large")
+ML = 1024  # leaves recorded per ray in the parity traces
 
 
 def log(*a):
@@ -73,6 +91,54 @@ def profiled_counts(variant, workload):
         except (KeyError, ValueError):
             out.append(None)
     return tuple(out)
+
+
+def roofline(alg_bytes, kernel_s, traffic_b, valu_instr, copy_bps):
+    """The roofline object of the cast kernel.
+
+    The kernel has no contraction (no MFMA) and, by its counters, moves far
+    fewer HBM bytes than it issues vector instructions for: the L2 serves
+    most of the node loads.  Its bound is then vector issue ("alu"):
+    achieved = wave64 VALU instructions per second (profiled count per launch
+    over the event-timed launch), peak = VALU_PEAK.  The HBM figures sit
+    beside it: the algorithmic bytes (16 B per pixel + 8 B per leaf payload
+    + 4 B per neighbour link or level descended, counted by the kernel) and
+    the measured HBM bytes, each over 8 TB/s."""
+    alg_bps = alg_bytes / kernel_s
+    traffic_bps = traffic_b / kernel_s if traffic_b else None
+    valu_rate = valu_instr / kernel_s if valu_instr else None
+    issue_frac = valu_rate / VALU_PEAK if valu_rate else None
+    hbm_frac = traffic_bps / HBM_PEAK if traffic_bps else None
+    if issue_frac is not None and hbm_frac is not None:
+        bound = "alu" if issue_frac >= hbm_frac else "hbm"
+    else:
+        bound = None  # the committed profile is of another build of the kernel
+    r = {"bound": bound}
+    if bound == "hbm":
+        r.update(achieved=round(traffic_bps / 1e9, 1), peak=HBM_PEAK / 1e9, unit="GB/s",
+                 frac=round(hbm_frac, 4))
+    elif bound == "alu":
+        r.update(achieved=round(valu_rate / 1e9, 1), peak=round(VALU_PEAK / 1e9, 1),
+                 unit="G wave64 VALU instr/s", frac=round(issue_frac, 4))
+    else:
+        r.update(achieved=None, peak=None, unit=None, frac=None)
+    r.update({
+        # HBM bytes per second from the committed profile (FETCH_SIZE +
+        # WRITE_SIZE, calibrated on a device copy)
+        "traffic": round(traffic_bps / 1e9, 1) if traffic_bps else None,
+        "traffic_unit": "GB/s",
+        "traffic_bytes_per_launch": traffic_b,
+        "hbm_measured_frac": round(hbm_frac, 4) if hbm_frac else None,
+        "alg_bytes_per_launch": alg_bytes,
+        "alg_GBps": round(alg_bps / 1e9, 1),
+        "alg_bytes_frac": round(alg_bps / HBM_PEAK, 4),
+        "kernel_ms": round(kernel_s * 1e3, 4),
+        "measured_copy_GBps": round(copy_bps / 1e9, 1) if copy_bps else None,
+        "alg_bytes_frac_of_measured_copy": round(alg_bps / copy_bps, 4) if copy_bps else None,
+        "valu_wave_instr_per_launch": valu_instr,
+        "valu_per_simd_cycle": round(valu_rate / (N_SIMD * CLOCK), 3) if valu_rate else None,
+    })
+    return r
 
 
 def build_workload(name, threads):
@@ -243,12 +309,187 @@ def stroke_bench(sess, cv, seed):
     return out
 
 
+def parity_check(sess, w, ids, img, variant):
+    """Leaf sequences and RGBA of `variant` against the oracle on the sampled
+    rays, and the naive canvas-global FP32 caster on the same rays."""
+    from oracle import oracle
+    views = w.views
+    orc = oracle.render(w.canvases, views, ids, max_leaves=ML)
+    skip = (orc["flags"] & (oracle.FLAG_NEAR_FACE | oracle.FLAG_TERM_AMBIG)) != 0
+    m = np.minimum(orc["n_leaves"], ML).astype(np.int64)
+    pos = np.arange(ML)[None, :] < m[:, None]
+
+    def seq_ok(gpu):
+        return (gpu["n_leaves"] == orc["n_leaves"]) & np.all(
+            (gpu["leaf_ids"] == orc["leaf_ids"]) | ~pos, axis=1)
+
+    gpu = sess.trace(views, ids, ML, variant)
+    vi = (ids >> np.uint64(32)).astype(np.int64)
+    px = (ids & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    offs = np.array([v["out_offset_px"] for v in views], np.int64)
+    pix = img[offs[vi] + px]
+    rgba_err = np.abs(pix.astype(np.float64) - orc["rgba"]).max(axis=1)
+    ok = seq_ok(gpu)
+    n = len(ids)
+    par = dict(rays=int(n), flagged=int(skip.sum()),
+               bit_exact_share=round(float((~skip).mean()), 4),
+               seq_mismatch=int((~ok & ~skip).sum()),
+               seq_mismatch_flagged=int((~ok & skip).sum()),
+               max_rgba_err=float(rgba_err[~skip].max()),
+               max_rgba_err_flagged=float(rgba_err[skip].max()) if skip.any() else 0.0,
+               trace_equals_render=bool(np.array_equal(gpu["rgba"], pix)),
+               gpu_fp64_exit_rays=int(((gpu["flags"] & 2) != 0).sum()),
+               mean_leaves=round(float(orc["n_leaves"].mean()), 1))
+    par["pass"] = (par["seq_mismatch"] == 0 and par["max_rgba_err"] <= 1e-3
+                   and par["trace_equals_render"])
+    naive = sess.trace(views, ids, ML, "fp32_naive")
+    nok = seq_ok(naive)
+    nerr = np.abs(naive["rgba"].astype(np.float64) - orc["rgba"]).max(axis=1)
+    nv = {"seq_mismatch": int((~nok & ~skip).sum()),
+          "seq_mismatch_rate": round(float((~nok & ~skip).sum() / max(1, (~skip).sum())), 4),
+          "max_rgba_err": float(nerr[~skip].max()),
+          "rays_over_1e-3": int((nerr[~skip] > 1e-3).sum())}
+    return par, nv, float(orc["alg_bytes"].mean())
+
+
+def run_workload(sess, name, args, headline, copy_bps):
+    """Every measurement of one workload; the pools are freed at the end."""
+    torch = sess.torch
+    steps = args.steps if headline else args.extra_steps
+    warmup = args.warmup if headline else 2
+    t = time.perf_counter()
+    w = build_workload(name, args.threads)
+    cv = w.canvases
+    log(f"[{name}] built: {[c.n_nodes for c in cv]} nodes in {time.perf_counter() - t:.1f}s")
+    views = w.views
+    rays = w.n_rays
+    t = time.perf_counter()
+    for i, c in enumerate(cv):
+        sess.upload(i, c)
+    log(f"[{name}] uploaded in {time.perf_counter() - t:.1f}s")
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    tuning = dict(tile=(tw, th), workgroups=args.workgroups, wg_size=args.wg_size)
+    tuning64 = dict(tuning)
+    if not args.no_autotune:
+        t = time.perf_counter()
+        reps = args.tune_reps if headline else 1
+        tuning, tune_rows = sess.autotune(views, args.variant, reps=reps)
+        log(f"[{name}] autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; "
+            "fastest: " + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}/q{r[6]}: "
+                                    f"{r[4]:.3f}ms"
+                                    for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
+        if args.fp64_steps > 0:
+            tuning64, _ = sess.autotune(views, "fp64_plain", reps=1)
+            log(f"[{name}] autotune fp64_plain: {tuning64}")
+
+    # --- timed: production variant
+    out, wall, per = time_variant(sess, views, args.variant, steps, warmup, tuning)
+    ms_step = wall * 1e3 / steps
+    value = rays / (ms_step * 1e-3) / 1e6
+    log(f"[{name}] {args.variant}: {ms_step:.3f} ms/step (events mean {per.mean():.3f}), "
+        f"{value:.1f} Mrays/s")
+
+    # --- algorithmic bytes of one launch, counted by the kernel (untimed)
+    st = sess.new_stats()
+    sess.render(views, args.variant, stats=st, **tuning)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy().astype(np.float64)
+    alg_bytes = 16.0 * s[0] + 8.0 * s[1] + 4.0 * (s[2] + s[3])
+    kernel_s = per.mean() * 1e-3
+
+    # --- FP64 plain baseline on the same GPU
+    fp64 = None
+    if args.fp64_steps > 0:
+        _, wall64, _ = time_variant(sess, views, "fp64_plain", args.fp64_steps, 1, tuning64)
+        fp64 = rays / (wall64 / args.fp64_steps) / 1e6
+        log(f"[{name}] fp64_plain: {wall64 * 1e3 / args.fp64_steps:.3f} ms/step, "
+            f"{fp64:.1f} Mrays/s")
+
+    # --- one launch per view, for the batching comparison
+    per_view = None
+    pv_steps = args.per_view_steps if args.per_view_steps >= 0 else (3 if len(views) > 2 else 0)
+    if pv_steps > 0:
+        pv_s, pv_out = time_per_view(sess, views, args.variant, pv_steps, tuning)
+        same = bool(torch.equal(pv_out, out))
+        per_view = dict(mrays=round(rays / pv_s / 1e6, 2), ms_per_step=round(pv_s * 1e3, 3),
+                        launches_per_step=len(views), steps=pv_steps,
+                        batched_speedup=round(pv_s / (ms_step * 1e-3), 3), same_image=same)
+        log(f"[{name}] per-view launches: {per_view}")
+        del pv_out
+
+    # --- parity on a seeded sample (sequences + RGBA) against the oracle, and
+    # the naive global-FP32 caster on the same rays
+    ids = sample_ids(views, args.parity_sample if headline else args.extra_parity_sample,
+                     12345)
+    img = out.cpu().numpy()
+    parity, naive, mean_b_oracle = parity_check(sess, w, ids, img, args.variant)
+    log(f"[{name}] parity: {parity}")
+    log(f"[{name}] naive fp32: {naive}")
+
+    res = dict(workload=name, views=len(views), rays_per_step=int(rays),
+               nodes=int(sum(c.n_nodes for c in cv)),
+               value=round(value, 2) if parity["pass"] else None,
+               value_unchecked=round(value, 2), ms_per_step=round(ms_step, 4), steps=steps,
+               tuning=dict(tile="%dx%d" % tuple(tuning["tile"]),
+                           workgroups=int(tuning["workgroups"]), wg_size=int(tuning["wg_size"]),
+                           top_lookup=int(tuning.get("top_lookup", 0)),
+                           single_queue=int(tuning.get("single_queue", 0)),
+                           autotuned=not args.no_autotune),
+               fp64_plain_mrays=round(fp64, 2) if fp64 else None,
+               speedup_vs_fp64_plain=round(value / fp64, 3) if fp64 else None,
+               per_view_launches=per_view, parity=parity, naive_fp32=naive,
+               alg_bytes_per_ray=alg_bytes / max(s[0], 1.0),
+               alg_bytes_per_ray_oracle_sample=mean_b_oracle,
+               alg_bytes_frac=round(alg_bytes / kernel_s / HBM_PEAK, 4),
+               kernel_ms=round(kernel_s * 1e3, 4),
+               kernel_stats=dict({k: int(v) for k, v in zip(
+                   ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase", "steps",
+                    "slots"], s[:8])},
+                   lane_occupancy=round(float(s[6] / s[7]), 4) if s[7] else None))
+    traffic_b, valu_instr = profiled_counts(args.variant, name)
+    res["roofline"] = roofline(alg_bytes, kernel_s, traffic_b, valu_instr, copy_bps)
+
+    if name == "depth24" and args.edit_bench:
+        res["pool_edit"] = edit_bench(sess, cv[0], 20000, 2000, 500, 99)
+        log(f"[{name}] pool edits: {res['pool_edit']}")
+        res["pool_edit"]["strokes"] = stroke_bench(sess, cv[0], 123)
+
+    # --- CPU oracle baseline (headline only): a bounded seeded sample
+    if headline and not args.no_cpu:
+        from oracle import oracle
+        n_all = sum(v["W"] * v["H"] for v in views)
+        cids = None if n_all <= args.cpu_sample else sample_ids(views, args.cpu_sample, 777)
+        n_cpu = n_all if cids is None else len(cids)
+        threads = min(16, os.cpu_count() or 1)
+        t = time.perf_counter()
+        oracle.render(cv, views, cids, threads=threads)
+        dt = time.perf_counter() - t
+        what = (f"every ray of the workload ({n_all})" if cids is None else
+                f"{n_cpu} seeded uniform rays of the same views")
+        res["cpu_baseline"] = dict(value=round(n_cpu / dt / 1e6, 4), unit="Mrays/s",
+                                   cores=threads, kind="oracle", sample=f"{what}, {dt:.1f}s wall")
+        log(f"[{name}] cpu oracle: {res['cpu_baseline']}")
+
+    for i in range(len(cv)):
+        sess.free(i)
+    del out, img, w, cv
+    gc.collect()
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="depth24")
+    ap.add_argument("--workload", default="large", choices=WORKLOADS)
+    ap.add_argument("--extra", default="depth24,depth30,batch",
+                    help="workloads measured after the headline one, reported under 'configs' "
+                         "(comma-separated; empty for none)")
+    ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--extra-parity-sample", type=int, default=32768)
     ap.add_argument("--variant", default="fp32_rebased")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--parity-sample", type=int, default=65536)
@@ -264,7 +505,8 @@ def main():
                     help="use --tile/--workgroups/--wg-size instead of cvx_autotune's pick")
     ap.add_argument("--tune-reps", type=int, default=3)
     ap.add_argument("--edit-bench", type=int, default=1,
-                    help="also time pool edits and brush strokes on the first canvas (0 skips them)")
+                    help="time pool edits and brush strokes on the depth-24 canvas when it is "
+                         "measured (0 skips them)")
     ap.add_argument("--per-view-steps", type=int, default=-1,
                     help="steps of the one-launch-per-view comparison (default 3 when the "
                          "workload has more than two views; 0 skips it)")
@@ -277,27 +519,15 @@ def main():
               "on one GPU; rays are independent, so more GPUs would split the tiles of a "
               "replicated pool", file=sys.stderr)
         sys.exit(2)
+    extras = [x for x in args.extra.split(",") if x]
+    for x in extras:
+        if x not in WORKLOADS:
+            raise SystemExit(f"unknown workload {x}")
 
     import torch
-    from oracle import oracle
     from paper_1704_02724_amd.session import Session
 
-    tw, th = (int(x) for x in args.tile.split("x"))
-    tuning = dict(tile=(tw, th), workgroups=args.workgroups, wg_size=args.wg_size)
-
-    t = time.perf_counter()
-    w = build_workload(args.workload, args.threads)
-    cv = w.canvases
-    log(f"built {args.workload}: {[c.n_nodes for c in cv]} nodes in {time.perf_counter() - t:.1f}s")
-    views = w.views
-    rays = w.n_rays
-
     sess = Session(0)
-    t = time.perf_counter()
-    for i, c in enumerate(cv):
-        sess.upload(i, c)
-    log(f"uploaded in {time.perf_counter() - t:.1f}s")
-
     copy_bps = None
     if args.copy_probe_mb:
         # measured HBM peak: a device-to-device copy (reads + writes), best of 5
@@ -318,167 +548,52 @@ def main():
         log(f"copy probe: {nb} bytes read + {nb} bytes written, best {best:.3f} ms, "
             f"{copy_bps / 1e9:.1f} GB/s")
         del src, dst
+        torch.cuda.empty_cache()
 
-    tuning64 = dict(tuning)
-    tune_rows = None
-    if not args.no_autotune:
-        t = time.perf_counter()
-        tuning, tune_rows = sess.autotune(views, args.variant, reps=args.tune_reps)
-        log(f"autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; fastest: "
-            + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}/q{r[6]}: {r[4]:.3f}ms"
-                        for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
-        by = {}
-        for r in tune_rows:
-            key = f"top{r[5]}/q{r[6]}"
-            by[key] = min(by.get(key, 1e30), r[4])
-        log("autotune best per (top lookup, queue) choice: "
-            + ", ".join(f"{k}: {v:.3f}ms" for k, v in sorted(by.items())))
-        if args.fp64_steps > 0:
-            tuning64, _ = sess.autotune(views, "fp64_plain", reps=max(1, args.tune_reps - 2))
-            log(f"autotune fp64_plain: {tuning64}")
-
-    # --- timed: production variant
-    out, wall, per = time_variant(sess, views, args.variant, args.steps, args.warmup, tuning)
-    ms_step = wall * 1e3 / args.steps
-    value = rays / (ms_step * 1e-3) / 1e6
-    log(f"{args.variant}: {ms_step:.3f} ms/step (events mean {per.mean():.3f}), {value:.1f} Mrays/s")
-
-    # --- algorithmic bytes of one launch, counted by the kernel (untimed)
-    st = sess.new_stats()
-    sess.render(views, args.variant, stats=st, **tuning)
-    torch.cuda.synchronize()
-    s = st.cpu().numpy().astype(np.float64)
-    alg_bytes = 16.0 * s[0] + 8.0 * s[1] + 4.0 * (s[2] + s[3])
-    kernel_s = per.mean() * 1e-3
-    achieved = alg_bytes / kernel_s
-    traffic_b, valu_instr = profiled_counts(args.variant, args.workload)
-
-    # --- FP64 plain baseline on the same GPU
-    fp64 = None
-    if args.fp64_steps > 0:
-        _, wall64, per64 = time_variant(sess, views, "fp64_plain", args.fp64_steps, 1, tuning64)
-        fp64 = rays / (wall64 / args.fp64_steps) / 1e6
-        log(f"fp64_plain: {wall64 * 1e3 / args.fp64_steps:.3f} ms/step, {fp64:.1f} Mrays/s")
-
-    # --- one launch per view, for the batching comparison
-    per_view = None
-    pv_steps = args.per_view_steps if args.per_view_steps >= 0 else (3 if len(views) > 2 else 0)
-    if pv_steps > 0:
-        pv_s, pv_out = time_per_view(sess, views, args.variant, pv_steps, tuning)
-        same = bool(torch.equal(pv_out, out))
-        per_view = dict(mrays=round(rays / pv_s / 1e6, 2), ms_per_step=round(pv_s * 1e3, 3),
-                        launches_per_step=len(views), steps=pv_steps,
-                        batched_speedup=round(pv_s / (ms_step * 1e-3), 3), same_image=same)
-        log(f"per-view launches: {per_view}")
-        del pv_out
-
-    # --- parity on a seeded sample (sequences + RGBA) against the oracle
-    ids = sample_ids(views, args.parity_sample, 12345)
-    ML = 1024
-    orc = oracle.render(cv, views, ids, max_leaves=ML)
-    gpu = sess.trace(views, ids, ML, args.variant)
-    skip = (orc["flags"] & (oracle.FLAG_NEAR_FACE | oracle.FLAG_TERM_AMBIG)) != 0
-    m = np.minimum(orc["n_leaves"], ML).astype(np.int64)
-    pos = np.arange(ML)[None, :] < m[:, None]
-    seq_ok = (gpu["n_leaves"] == orc["n_leaves"]) & np.all(
-        (gpu["leaf_ids"] == orc["leaf_ids"]) | ~pos, axis=1)
-    img = out.cpu().numpy()
-    vi = (ids >> np.uint64(32)).astype(np.int64)
-    px = (ids & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    offs = np.array([v["out_offset_px"] for v in views], np.int64)
-    rgba_err = np.abs(img[offs[vi] + px].astype(np.float64) - orc["rgba"]).max(axis=1)
-    parity = dict(rays=int(len(ids)), flagged=int(skip.sum()),
-                  seq_mismatch=int((~seq_ok & ~skip).sum()),
-                  max_rgba_err=float(rgba_err[~skip].max()),
-                  max_rgba_err_flagged=float(rgba_err[skip].max()) if skip.any() else 0.0,
-                  gpu_fp64_exit_rays=int(((gpu["flags"] & 2) != 0).sum()))
-    parity["pass"] = parity["seq_mismatch"] == 0 and parity["max_rgba_err"] <= 1e-3
-    mean_b_oracle = float(orc["alg_bytes"].mean())
-    log(f"parity: {parity}")
-
-    # --- pool edits on a copy of the first canvas
-    edit = None
-    if args.edit_bench:
-        edit = edit_bench(sess, cv[0], 20000, 2000, 500, 99)
-        log(f"pool edits: {edit}")
-        edit["strokes"] = stroke_bench(sess, cv[0], 123)
-
-    # --- CPU oracle baseline: the whole workload, or a bounded sample of it
-    cpu = None
-    if not args.no_cpu:
-        n_all = sum(v["W"] * v["H"] for v in views)
-        cids = None if n_all <= args.cpu_sample else sample_ids(views, args.cpu_sample, 777)
-        n_cpu = n_all if cids is None else len(cids)
-        threads = min(16, os.cpu_count() or 1)
-        t = time.perf_counter()
-        oracle.render(cv, views, cids, threads=threads)
-        dt = time.perf_counter() - t
-        what = (f"every ray of the workload ({n_all})" if cids is None else
-                f"{n_cpu} seeded uniform rays of the same views")
-        cpu = dict(value=round(n_cpu / dt / 1e6, 4), unit="Mrays/s", cores=threads,
-                   kind="oracle", sample=f"{what}, {dt:.1f}s wall")
-        log(f"cpu oracle: {cpu}")
+    head = run_workload(sess, args.workload, args, True, copy_bps)
+    configs = {}
+    for x in extras:
+        r = run_workload(sess, x, args, False, copy_bps)
+        configs[x] = {k: r[k] for k in (
+            "value", "value_unchecked", "ms_per_step", "rays_per_step", "views", "nodes",
+            "fp64_plain_mrays", "speedup_vs_fp64_plain", "alg_bytes_frac", "parity",
+            "naive_fp32", "per_view_launches", "tuning", "kernel_stats")}
+        configs[x]["roofline"] = {k: r["roofline"][k] for k in (
+            "bound", "frac", "alg_bytes_frac", "hbm_measured_frac", "valu_per_simd_cycle")}
+        if "pool_edit" in r:
+            configs[x]["pool_edit"] = r["pool_edit"]
+    sess.close()
 
     res = {
-        "metric": "Mrays/s at \u22641e-3 RGBA err vs FP64 oracle "
+        "metric": "Mrays/s at ≤1e-3 RGBA err vs FP64 oracle "
                   "(FP32-rebased batched vs FP64 plain)",
-        "value": round(value, 2),
+        "value": head["value"],
         "unit": "Mrays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "views": len(views),
-            "rays_per_step": int(rays),
-            "nodes": int(sum(c.n_nodes for c in cv)),
-            "variant": args.variant,
-            "tile": "%dx%d" % tuple(tuning["tile"]) if tuning["tile"][0] else args.tile,
-            "workgroups": int(tuning["workgroups"]),
-            "wg_size": int(tuning["wg_size"]),
-            "top_lookup": int(tuning.get("top_lookup", 0)),
-            "single_queue": int(tuning.get("single_queue", 0)),
-            "autotuned": not args.no_autotune,
-            "graph": True,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved / 1e9, 1),
-            "peak": HBM_PEAK / 1e9,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK, 4),
-            "traffic": (round(traffic_b / kernel_s / 1e9, 1) if traffic_b else None),
-            "traffic_bytes_per_launch": traffic_b,
-            "alg_bytes_per_launch": alg_bytes,
-            "alg_bytes_per_ray": alg_bytes / max(s[0], 1.0),
-            "alg_bytes_per_ray_oracle_sample": mean_b_oracle,
-            "kernel_ms": round(per.mean(), 4),
-            "kernel_ms_median": round(float(np.median(per)), 4),
-            "measured_copy_GBps": round(copy_bps / 1e9, 1) if copy_bps else None,
-            "frac_of_measured_copy": round(achieved / copy_bps, 4) if copy_bps else None,
-            # vector issue, the measured limit: wave64 VALU instructions per
-            # launch (profile) per SIMD-cycle at 2.4 GHz over 1024 SIMDs
-            "valu_wave_instr_per_launch": valu_instr,
-            "valu_per_simd_cycle": (round(valu_instr / (kernel_s * 1024 * 2.4e9), 3)
-                                    if valu_instr else None),
-        },
-        "fp64_plain_mrays": round(fp64, 2) if fp64 else None,
-        "speedup_vs_fp64_plain": round(value / fp64, 3) if fp64 else None,
-        "per_view_launches": per_view,
-        "pool_edit": edit,
-        "parity": parity,
-        "kernel_stats": dict({k: int(v) for k, v in zip(
-            ["rays", "leaves", "outer", "descent", "fp64_exit", "rebase", "steps", "slots"], s[:8])},
-            lane_occupancy=round(float(s[6] / s[7]), 4) if s[7] else None),
-        "cpu_baseline": cpu,
+        "config": dict({"workload": args.workload, "views": head["views"],
+                        "rays_per_step": head["rays_per_step"], "nodes": head["nodes"],
+                        "variant": args.variant, "graph": True}, **head["tuning"]),
+        "roofline": head["roofline"],
+        "value_unchecked": head["value_unchecked"],
+        "fp64_plain_mrays": head["fp64_plain_mrays"],
+        "speedup_vs_fp64_plain": head["speedup_vs_fp64_plain"],
+        "per_view_launches": head["per_view_launches"],
+        "parity": head["parity"],
+        "naive_fp32": head["naive_fp32"],
+        "alg_bytes_per_ray": head["alg_bytes_per_ray"],
+        "alg_bytes_per_ray_oracle_sample": head["alg_bytes_per_ray_oracle_sample"],
+        "kernel_stats": head["kernel_stats"],
+        "cpu_baseline": head.get("cpu_baseline"),
+        "configs": configs,
     }
-    sess.close()
     print(json.dumps(res), flush=True)
 
 
