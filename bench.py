@@ -376,9 +376,13 @@ def run_workload(sess, name, args, headline, copy_bps):
         reps = args.tune_reps if headline else 1
         tuning, tune_rows = sess.autotune(views, args.variant, reps=reps)
         log(f"[{name}] autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; "
-            "fastest: " + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}/q{r[6]}: "
-                                    f"{r[4]:.3f}ms"
+            "fastest: " + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}/q{r[6]}/"
+                                    f"rpw{r[7]}/min{r[8]}: {r[4]:.3f}ms"
                                     for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
+        refill_rows = [r for r in tune_rows if r[7] > 64]
+        if refill_rows:
+            log(f"[{name}] lane refill on the fastest shape: "
+                + ", ".join(f"rpw{r[7]}/min{r[8]}: {r[4]:.3f}ms" for r in refill_rows))
         if args.fp64_steps > 0:
             tuning64, _ = sess.autotune(views, "fp64_plain", reps=1)
             log(f"[{name}] autotune fp64_plain: {tuning64}")
@@ -435,6 +439,8 @@ def run_workload(sess, name, args, headline, copy_bps):
                            workgroups=int(tuning["workgroups"]), wg_size=int(tuning["wg_size"]),
                            top_lookup=int(tuning.get("top_lookup", 0)),
                            single_queue=int(tuning.get("single_queue", 0)),
+                           rays_per_wave=int(tuning.get("rays_per_wave", 64)),
+                           refill_min=int(tuning.get("refill_min", 0)),
                            autotuned=not args.no_autotune),
                fp64_plain_mrays=round(fp64, 2) if fp64 else None,
                speedup_vs_fp64_plain=round(value / fp64, 3) if fp64 else None,

@@ -157,6 +157,15 @@ typedef struct {
                             pool is read with 64-bit addresses, the code that pools above
                             2^28 nodes always take (same result; for checking that code on
                             any pool) */
+  uint32_t rays_per_wave; /* FP32_REBASED renders (not trace or stats): rays one wavefront
+                            takes per work item, a multiple of 64 up to 1024 (0 = 64).  64:
+                            one tile, one ray per lane, the wavefront ends the item with its
+                            longest ray.  Above 64: up to rays_per_wave / 64 consecutive
+                            tiles of one view, and lanes whose ray ended take the item's next
+                            rays (assigned by a wavefront ballot) once refill_min lanes wait
+                            (Sec. 6.2: a ray stops at full opacity or at the canvas exit;
+                            refilling keeps the other lanes busy).  Same result. */
+  uint32_t refill_min;  /* lanes that must wait before they are refilled, 1..64 (0 = 32) */
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;
@@ -231,6 +240,8 @@ typedef struct {
   float ms;                /* mean time of one render, milliseconds */
   uint32_t top_lookup;     /* as in cvx_render_opts */
   uint32_t single_queue;   /* as in cvx_render_opts */
+  uint32_t rays_per_wave;  /* as in cvx_render_opts (64: no refill) */
+  uint32_t refill_min;     /* as in cvx_render_opts (0 when rays_per_wave is 64) */
   uint32_t reserved;
 } cvx_tune_result;
 
@@ -239,7 +250,10 @@ typedef struct {
  * tile shape (8x8, 16x4, 4x16, 32x2), workgroup size (64, 128, 256),
  * persistent grid (16, 28, 32, 64 wavefronts per CU), top-level lookup
  * (on, off) and work queues (per XCD, single), one untimed warm-up
- * then `reps` renders timed with HIP events on the context stream.  Writes
+ * then `reps` renders timed with HIP events on the context stream.  For
+ * FP32_REBASED the fastest of those shapes is then timed with lane refill,
+ * rays_per_wave 128 and 256 with refill_min 16, 32 and 48, which are
+ * candidates like the others.  Writes
  * base with the fastest shape filled in to *best and, when results is not
  * NULL, up to max_results timed candidates in the order tried (the count
  * tried goes to *n_results when not NULL).  out_dev receives the renders

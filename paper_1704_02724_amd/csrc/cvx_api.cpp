@@ -19,13 +19,14 @@ using cvx::DevCanvas;
 using cvx::DView;
 
 struct GraphKey {
-  uint32_t variant = ~0u, tw = 0, th = 0, wgs = 0, wg = 0;
+  uint32_t variant = ~0u, tw = 0, th = 0, wgs = 0, wg = 0, item_tiles = 1, refill_min = 0;
   bool trace = false, stats = false, out64 = false, small = false, per_ray_start = false;
   const void* out = nullptr;
   const void* stats_ptr = nullptr;
   const void* views = nullptr;
   bool operator==(const GraphKey& o) const {
     return variant == o.variant && tw == o.tw && th == o.th && wgs == o.wgs && wg == o.wg &&
+           item_tiles == o.item_tiles && refill_min == o.refill_min &&
            trace == o.trace && stats == o.stats && out64 == o.out64 && small == o.small &&
            per_ray_start == o.per_ray_start &&
            out == o.out && stats_ptr == o.stats_ptr && views == o.views;
@@ -318,6 +319,7 @@ namespace {
 // Launch shape and mode of one render call, from its options.
 struct RenderPlan {
   uint32_t tw = 8, th = 8, wg = 256, wgs = 0;
+  uint32_t item_tiles = 1, refill_min = 32;  // lane refill of the FP32 render (item_tiles > 1)
 };
 
 // Checks the options and views of a render call (nothing is launched on an
@@ -339,6 +341,14 @@ int render_check(cvx_ctx* ctx, const cvx_view* views, int n_views, const void* o
   if (o.single_queue > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "single_queue must be 0 or 1");
   if (o.per_ray_start > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "per_ray_start must be 0 or 1");
   if (o.wide_offsets > 1) return fail(ctx, CVX_ERR_INVALID_ARG, "wide_offsets must be 0 or 1");
+  const uint32_t rpw = o.rays_per_wave ? o.rays_per_wave : 64u;
+  if (rpw % 64u != 0 || rpw > 1024u)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "rays_per_wave must be a multiple of 64 up to 1024");
+  if (o.refill_min > 64) return fail(ctx, CVX_ERR_INVALID_ARG, "refill_min must be in 0..64");
+  // trace and stats renders run one ray per lane (the same per-ray results)
+  const bool refill = o.variant == CVX_VARIANT_FP32_REBASED && !o.trace && !o.stats && rpw > 64u;
+  p.item_tiles = refill ? rpw / 64u : 1u;
+  p.refill_min = refill ? (o.refill_min ? o.refill_min : 32u) : 0u;
   if (o.out_f64 && o.variant != CVX_VARIANT_FP64_PLAIN)
     return fail(ctx, CVX_ERR_INVALID_ARG, "out_f64 needs the FP64_PLAIN variant");
   const cvx_trace* tr = o.trace;
@@ -411,8 +421,10 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     dv.alpha_stop = v.alpha_stop;
     dv.tiles_x = (v.W + p.tw - 1) / p.tw;
     uint64_t tiles_y = (v.H + p.th - 1) / p.th;
+    // work items before this view: tiles, or with lane refill groups of
+    // item_tiles tiles (an item never straddles views)
     dv.first_tile = first;
-    first += (uint64_t)dv.tiles_x * tiles_y;
+    first += ((uint64_t)dv.tiles_x * tiles_y + p.item_tiles - 1) / p.item_tiles;
     uint64_t cap = 3ull * c.desc.R * (1ull << std::min<uint32_t>(c.depth, 40)) + 16;
     dv.max_steps = (uint32_t)std::min<uint64_t>(cap, 1ull << 22);
     dv.n_nodes = (uint32_t)c.n_nodes;
@@ -447,6 +459,8 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   a.stats = o.stats;
   a.tile_w = p.tw;
   a.tile_h = p.th;
+  a.item_tiles = p.item_tiles;
+  a.refill_min = p.refill_min;
   a.small_pools = o.wide_offsets ? 0u : 1u;
   for (int i = 0; i < n_views; ++i)
     if (ctx->canvases[views[i].canvas_id].n_nodes > (1ull << 28)) a.small_pools = 0;
@@ -479,6 +493,8 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   key.th = p.th;
   key.wgs = p.wgs;
   key.wg = p.wg;
+  key.item_tiles = p.item_tiles;
+  key.refill_min = p.refill_min;
   key.trace = false;
   key.stats = stats;
   key.out64 = o.out_f64 != 0;
@@ -1362,6 +1378,42 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
   float best_ms = 0.0f;
   bool have = false;
   uint32_t count = 0;
+  // one untimed render (it also captures the graph), then reps timed ones
+  auto time_candidate = [&](const cvx_render_opts& o, float& ms) -> int {
+    int r = cvx_render(ctx, views, n_views, out_dev, &o);
+    if (r != CVX_OK) return r;
+    if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess)
+      return hip_fail(ctx, he, "hipEventRecord");
+    for (uint32_t i = 0; i < reps && r == CVX_OK; ++i) r = cvx_render(ctx, views, n_views, out_dev, &o);
+    if (r != CVX_OK) return r;
+    if ((he = hipEventRecord(e1, ctx->stream)) != hipSuccess ||
+        (he = hipEventSynchronize(e1)) != hipSuccess ||
+        (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+      return hip_fail(ctx, he, "timing a candidate");
+    ms /= (float)reps;
+    return CVX_OK;
+  };
+  auto record = [&](const cvx_render_opts& o, float ms) {
+    if (count < max_results) {
+      cvx_tune_result& x = results[count];
+      x.tile_w = o.tile_w;
+      x.tile_h = o.tile_h;
+      x.wg_size = o.wg_size;
+      x.workgroups = o.workgroups;
+      x.ms = ms;
+      x.top_lookup = o.top_lookup;
+      x.single_queue = o.single_queue;
+      x.rays_per_wave = o.rays_per_wave ? o.rays_per_wave : 64u;
+      x.refill_min = o.rays_per_wave > 64u ? o.refill_min : 0u;
+      x.reserved = 0;
+    }
+    ++count;
+    if (!have || ms < best_ms) {
+      have = true;
+      best_ms = ms;
+      *best = o;
+    }
+  };
   for (uint32_t sq : kQueue) {
   for (uint32_t top : kTop) {
   for (const auto& t : kTiles) {
@@ -1375,43 +1427,34 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         o.workgroups = (uint32_t)ctx->n_cu * wpc * 64u / wg;
         o.top_lookup = top;
         o.single_queue = sq;
-        rc = cvx_render(ctx, views, n_views, out_dev, &o);  // warm-up, captures the graph
-        if (rc != CVX_OK) break;
-        if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess) {
-          rc = hip_fail(ctx, he, "hipEventRecord");
-          break;
-        }
-        for (uint32_t r = 0; r < reps && rc == CVX_OK; ++r)
-          rc = cvx_render(ctx, views, n_views, out_dev, &o);
-        if (rc != CVX_OK) break;
+        o.rays_per_wave = 0;
+        o.refill_min = 0;
         float ms = 0.0f;
-        if ((he = hipEventRecord(e1, ctx->stream)) != hipSuccess ||
-            (he = hipEventSynchronize(e1)) != hipSuccess ||
-            (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
-          rc = hip_fail(ctx, he, "timing a candidate");
-          break;
-        }
-        ms /= (float)reps;
-        if (count < max_results) {
-          cvx_tune_result& x = results[count];
-          x.tile_w = o.tile_w;
-          x.tile_h = o.tile_h;
-          x.wg_size = o.wg_size;
-          x.workgroups = o.workgroups;
-          x.ms = ms;
-          x.top_lookup = o.top_lookup;
-          x.single_queue = o.single_queue;
-        }
-        ++count;
-        if (!have || ms < best_ms) {
-          have = true;
-          best_ms = ms;
-          *best = o;
-        }
+        rc = time_candidate(o, ms);
+        if (rc != CVX_OK) break;
+        record(o, ms);
       }
     }
   }
   }
+  }
+  // lane refill on the fastest shape (FP32 renders only)
+  if (rc == CVX_OK && have && b.variant == CVX_VARIANT_FP32_REBASED) {
+    static const uint32_t kRpw[] = {128, 256};
+    static const uint32_t kMin[] = {16, 32, 48};
+    const cvx_render_opts shape = *best;
+    for (uint32_t rpw : kRpw) {
+      for (uint32_t mn : kMin) {
+        if (rc != CVX_OK) break;
+        cvx_render_opts o = shape;
+        o.rays_per_wave = rpw;
+        o.refill_min = mn;
+        float ms = 0.0f;
+        rc = time_candidate(o, ms);
+        if (rc != CVX_OK) break;
+        record(o, ms);
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

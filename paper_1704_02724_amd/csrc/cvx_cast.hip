@@ -34,6 +34,9 @@
 #ifndef CVX_CAST32_WAVES
 #define CVX_CAST32_WAVES 8
 #endif
+#ifndef CVX_CAST32R_WAVES
+#define CVX_CAST32R_WAVES 7
+#endif
 
 namespace cvx {
 
@@ -344,6 +347,12 @@ __device__ __forceinline__ T opaque(T x) {
   return x;
 }
 
+// The same for a wavefront-uniform value held in a scalar register.
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 __device__ __forceinline__ float kappa_of(uint2 p) {
   return (float)__builtin_bit_cast(_Float16, (unsigned short)(p.y & 0xffffu));
 }
@@ -401,46 +410,55 @@ struct RaySlot {
   __device__ __forceinline__ double at(int j) const { return opaque(p)[j * stride]; }
 };
 
-template <bool TRACE, bool STATS, bool SMALL>
-__device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& o,
-                          const V3<double>& d, const V3<double>& inv, const Entry& en,
-                          const V3<bool>& up, Sink sk, Acc& acc, Out& out) {
-  const double Rd = (double)v.R;
+// Work of one wavefront in the refilling render kernel: the rays of up to
+// `item_tiles` consecutive tiles of one view, numbered 64 per tile.  A lane
+// whose ray ends waits until at least `refill_min` lanes of the wavefront
+// wait; then each waiting lane takes the next ray of the item that is not
+// taken yet (a wavefront ballot of the waiting lanes gives each its rank).
+struct RefillJob {
+  float4* out;
+  uint64_t first_tile;  // the item's first tile within its view
+  uint32_t n_rays;      // 64 x its tiles
+  uint32_t tile_w, tile_h;
+  uint32_t refill_min;
+};
+
+// FP32_REBASED traversal of one lane: one ray (REFILL = false: o, d, inv,
+// en, up describe it) or, REFILL = true, the rays a RefillJob hands out one
+// after another, each written to its pixel when it ends.  The per-ray
+// arithmetic is the same in both, so both give the same pixels.
+template <bool TRACE, bool STATS, bool SMALL, bool REFILL = false>
+__device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& o_in,
+                          const V3<double>& d_in, const V3<double>& inv_in, const Entry& en_in,
+                          const V3<bool>& up_in, Sink sk, Acc& acc, Out& out,
+                          const RefillJob* job = nullptr) {
   const void* rec = v.rec;
   const void* payp = v.pay;
-  slot.put(o, d, inv);
-  V3<float> tD;
-  for (int k = 0; k < 3; ++k) {
-    const double dk = get(d, k);
-    set(tD, k, __builtin_fabs(dk) >= 0x1p-60 ? 1.0f / __builtin_fabsf((float)dk) : 0.0f);
-  }
-  const bool anypar = tD.x == 0.0f || tD.y == 0.0f || tD.z == 0.0f;
-  const float tR = (float)(en.t1 + Rd + 1.0);
   const bool use_stop = v.alpha_stop < 1.0f;
-
-  // first leaf: the view's shared eye leaf, else FP64 point location from the
-  // top-level table or the root array (descended to the leaf by the rebase)
+  V3<float> tD;
+  bool anypar = false;
+  float tR = 0.0f;
+  V3<bool> up;
   V3<double> q;
-  for (int k = 0; k < 3; ++k) {
-    double qk = get(o, k) + en.t0 * get(d, k);
-    if (k == en.kin) qk = en.side ? Rd : 0.0;
-    set(q, k, qk < 0.0 ? 0.0 : (qk > Rd ? Rd : qk));
-  }
-  uint32_t I, dep = 0;
+  uint32_t I = 0, dep = 0;
   V3<uint32_t> c;
   uint4 r;
-  start_leaf(v, q, up, I, dep, c, r);
-  if (STATS) acc.descent += dep;
   uint2 pay = make_uint2(0u, 0u);
-
   uint32_t db = 0, w = 1;
   V3<float> S0{0.f, 0.f, 0.f};
   V3<int32_t> Nk{0, 0, 0};
   float s_ent = 0.0f, e_ent = 0.0f, betac = 0.0f;  // betac = BETA_C beta
-  // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
-  // current cell I is descended first when it is refined.
   bool bad = false;  // a node index outside the pool (never for a validated pool)
   double te_last = 0.0;  // trace mode: ray parameter of the last rebase
+  float T = 1.0f;
+  V3<float> C{0.f, 0.f, 0.f};
+  uint32_t n_rec = 0;
+  int ke = -1;  // axis of the face the current cell was entered through
+  uint32_t ub = 0;
+  uint32_t step = 0;
+  uint32_t end_Nn = 0, end_nc = 0, end_dep = 0;  // the move the ray ended on
+  // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
+  // current cell I is descended first when it is refined.
   auto rebase = [&](double te) __attribute__((always_inline)) {
     if (TRACE) te_last = te;
     const uint32_t d0 = dep;
@@ -465,20 +483,123 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     betac = beta * BETA_C;
     if (STATS) acc.rebase++;
   };
-  rebase(en.t0);
-
-  float T = 1.0f;
-  V3<float> C{0.f, 0.f, 0.f};
-  uint32_t n_rec = 0;
-  int ke = en.kin;  // axis of the face the current cell was entered through
-  uint32_t rstride[3] = {1u, v.R, v.R * v.R};
-  // travel direction bits (x | y<<1 | z<<2) in one opaque register: the
-  // exit-axis bit is one bit-field extract, not a chain of selects
-  const uint32_t ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
-  uint32_t step = 0;
-  uint32_t end_Nn = 0, end_nc = 0, end_dep = 0;  // the move the ray ended on
+  // ray start: the FP64 entry point, the first leaf and the first frame (Rd =
+  // the canvas side R in FP64)
+  auto begin = [&](const V3<double>& o, const V3<double>& d, const V3<double>& inv,
+                   const Entry& en, const V3<bool>& up_, double Rd) __attribute__((always_inline)) {
+    slot.put(o, d, inv);
+    for (int k = 0; k < 3; ++k) {
+      const double dk = get(d, k);
+      set(tD, k, __builtin_fabs(dk) >= 0x1p-60 ? 1.0f / __builtin_fabsf((float)dk) : 0.0f);
+    }
+    anypar = tD.x == 0.0f || tD.y == 0.0f || tD.z == 0.0f;
+    tR = (float)(en.t1 + Rd + 1.0);
+    up = up_;
+    // first leaf: the view's shared eye leaf, else FP64 point location from
+    // the top-level table or the root array (descended to the leaf by the
+    // rebase)
+    for (int k = 0; k < 3; ++k) {
+      double qk = get(o, k) + en.t0 * get(d, k);
+      if (k == en.kin) qk = en.side ? Rd : 0.0;
+      set(q, k, qk < 0.0 ? 0.0 : (qk > Rd ? Rd : qk));
+    }
+    dep = 0;
+    start_leaf(v, q, up, I, dep, c, r);
+    if (STATS) acc.descent += dep;
+    pay = make_uint2(0u, 0u);
+    db = 0;
+    w = 1;
+    bad = false;
+    te_last = 0.0;
+    rebase(en.t0);
+    T = 1.0f;
+    C = V3<float>{0.f, 0.f, 0.f};
+    n_rec = 0;
+    ke = en.kin;
+    // travel direction bits (x | y<<1 | z<<2) in one opaque register: the
+    // exit-axis bit is one bit-field extract, not a chain of selects
+    ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
+    step = 0;
+    end_Nn = end_nc = end_dep = 0;
+  };
+  // flags, colour and counts of the ray that ended
+  auto finish = [&]() __attribute__((always_inline)) {
+    if (bad)
+      out.flags |= CVX_RAYFLAG_BAD_LINK;
+    else if (step >= v.max_steps)
+      out.flags |= CVX_RAYFLAG_STEP_CAP;
+    else if (end_Nn >= v.n_nodes && end_nc < (v.R << end_dep))
+      out.flags |= CVX_RAYFLAG_BAD_LINK;  // a null link inside the canvas
+    const float k255 = 1.0f / 255.0f;
+    out.rgba[0] = C.x * k255;
+    out.rgba[1] = C.y * k255;
+    out.rgba[2] = C.z * k255;
+    out.rgba[3] = 1.0f - T;
+    out.n = n_rec;
+    out.steps = step + 1;
+    if (STATS) acc.leaves += n_rec;
+  };
+  // REFILL: the pixel of the lane's current ray; starting ray i of the job
+  // (false when its pixel lies outside the view, or when the ray misses the
+  // canvas: its pixel is then written as zero)
+  uint32_t px = 0, py = 0;
+  auto write_pixel = [&]() __attribute__((always_inline)) {
+    job->out[v.out_off + (uint64_t)py * v.W + px] = make_float4(
+        (float)out.rgba[0], (float)out.rgba[1], (float)out.rgba[2], (float)out.rgba[3]);
+  };
+  auto begin_job_ray = [&](uint32_t i) __attribute__((always_inline)) -> bool {
+    const uint64_t t = job->first_tile + i / 64u;
+    const uint32_t l = i % 64u;
+    px = (uint32_t)(t % v.tiles_x) * job->tile_w + l % job->tile_w;
+    py = (uint32_t)(t / v.tiles_x) * job->tile_h + l / job->tile_w;
+    if (px >= v.W || py >= v.H) return false;
+    // the view's sizes pass an opaque barrier here, so that their FP64
+    // conversions stay on this path instead of living (in vector registers)
+    // through the traversal loop
+    DView vr = v;
+    vr.W = opaque_s(v.W);
+    vr.H = opaque_s(v.H);
+    const double Rd = (double)opaque_s(v.R);
+    const V3<double> d = ray_dir(vr, px, py);
+    const V3<double> o{v.o[0], v.o[1], v.o[2]};
+    const V3<double> inv{1.0 / d.x, 1.0 / d.y, 1.0 / d.z};
+    const Entry en = canvas_entry(o, d, inv, Rd);
+    out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
+    out.flags = 0;
+    if (!en.hit) {
+      write_pixel();
+      return false;
+    }
+    begin(o, d, inv, en, V3<bool>{d.x > 0.0, d.y > 0.0, d.z > 0.0}, Rd);
+    return true;
+  };
+  bool alive = true;
+  uint32_t next = 64;     // REFILL: rays of the job handed out so far
+  uint32_t wait_for = 0;  // REFILL: waiting lanes that end a traversal round
+  if constexpr (REFILL) {
+    alive = begin_job_ray(threadIdx.x & 63u);
+    wait_for = job->refill_min;
+  } else {
+    begin(o_in, d_in, inv_in, en_in, up_in, (double)v.R);
+  }
+  // REFILL: rounds of traversal; a round ends when wait_for lanes wait, then
+  // the waiting lanes take the job's next rays (ranked by a ballot), and once
+  // none is left the last round runs until every lane waits.  The ray set-up
+  // stays out of the traversal loop.
+  for (;;) {
   for (;; ++step) {
-    if (step >= v.max_steps || bad) break;
+    if constexpr (REFILL) {
+      // every lane of the wavefront is here (uniform count)
+      if ((uint32_t)__popcll(__ballot(!alive)) >= wait_for) break;
+      if (!alive) continue;
+    }
+    if (step >= v.max_steps || bad) {
+      if constexpr (!REFILL) break;
+      finish();
+      write_pixel();
+      alive = false;
+      continue;
+    }
     // s-values of the far planes (leaf) or of the mid-planes (refined cell)
     // and their error bounds; a refined cell's mid-plane lies half a cell
     // before its far plane
@@ -604,7 +725,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       if (root) {
         // root array (rare): kept as a branch, not flattened into selects
         asm volatile("");
-        const uint32_t rs = mx ? rstride[0] : (my ? rstride[1] : rstride[2]);
+        const uint32_t rs = mx ? 1u : (my ? v.R : v.R * v.R);
         sib = nc >= v.R ? CVX_NONE : (upk ? I + rs : I - rs);
       }
       const uint32_t link = mx ? r.y : (my ? r.z : r.w);
@@ -615,7 +736,11 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         end_Nn = Nn;
         end_nc = nc;
         end_dep = dep;
-        break;
+        if constexpr (!REFILL) break;
+        finish();
+        write_pixel();
+        alive = false;
+        continue;
       }
       if (STATS) acc.outer += !inner;
       I = Nn;
@@ -654,20 +779,25 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       rebase(te);
     }
   }
-  if (bad)
-    out.flags |= CVX_RAYFLAG_BAD_LINK;
-  else if (step >= v.max_steps)
-    out.flags |= CVX_RAYFLAG_STEP_CAP;
-  else if (end_Nn >= v.n_nodes && end_nc < (v.R << end_dep))
-    out.flags |= CVX_RAYFLAG_BAD_LINK;  // a null link inside the canvas
-  const float k255 = 1.0f / 255.0f;
-  out.rgba[0] = C.x * k255;
-  out.rgba[1] = C.y * k255;
-  out.rgba[2] = C.z * k255;
-  out.rgba[3] = 1.0f - T;
-  out.n = n_rec;
-  out.steps = step + 1;
-  if (STATS) acc.leaves += n_rec;
+  if constexpr (!REFILL) {
+    finish();
+    return;
+  } else {
+    const uint64_t waiting = __ballot(!alive);
+    const uint32_t n_wait = (uint32_t)__popcll(waiting);
+    if (next >= job->n_rays) {
+      if (n_wait == 64u) return;
+      wait_for = 64;  // no ray left: finish the ones in flight
+      continue;
+    }
+    if (!alive) {
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(waiting >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)waiting, 0u));
+      if (next + rank < job->n_rays) alive = begin_job_ray(next + rank);
+    }
+    next += n_wait;
+  }
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -1134,6 +1264,55 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
   }
 }
 
+// The FP32 render with lane refill: a work item is up to a.item_tiles
+// consecutive tiles of one view (items never straddle views, so the view
+// stays wavefront-uniform), whose rays the wavefront's lanes take in turn
+// (RefillJob).  Per-view item counts replace tile counts in the views'
+// prefix sums (first_tile) and in the header's total.
+template <bool SMALL>
+__device__ __forceinline__ void cast_grid_refill(const CastArgs& a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t total = a.hdr->total_work;
+  const uint32_t nv = a.hdr->n_views;
+  const uint32_t nq = a.hdr->n_queues;  // 1 or CVX_NQ (a power of two)
+  const RaySlot slot{(lds_f64*)(s_ray + threadIdx.x), blockDim.x};
+  uint32_t qi = blockIdx.x & (nq - 1u), drained = 0;
+  for (;;) {
+    const uint64_t q_lo = total * qi / nq, q_hi = total * (qi + 1u) / nq;
+    uint32_t taken = 0;
+    if (lane == 0) taken = atomicAdd(&a.hdr->queue[qi].next, 1u);
+    taken = __builtin_amdgcn_readfirstlane(taken);
+    if (q_lo + taken >= q_hi) {
+      if (++drained == nq) break;
+      qi = (qi + 1u) & (nq - 1u);
+      continue;
+    }
+    const uint32_t w = (uint32_t)(q_lo + taken);
+    int lo = 0, hi = (int)nv - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (a.views[mid].first_tile <= (uint64_t)w) lo = mid; else hi = mid - 1;
+    }
+    const DView v = uniform_view(a.views[lo]);
+    const uint64_t tiles = (uint64_t)v.tiles_x * ((v.H + a.tile_h - 1u) / a.tile_h);
+    RefillJob job;
+    job.out = (float4*)a.out;
+    job.first_tile = ((uint64_t)w - v.first_tile) * a.item_tiles;
+    const uint64_t nt = tiles - job.first_tile < a.item_tiles ? tiles - job.first_tile : a.item_tiles;
+    job.n_rays = (uint32_t)nt * 64u;
+    job.tile_w = a.tile_w;
+    job.tile_h = a.tile_h;
+    job.refill_min = a.refill_min;
+    Out res;
+    Acc acc = {0, 0, 0, 0, 0, 0, 0, 0};
+    Sink sk{nullptr, nullptr, nullptr, 0};
+    const V3<double> z{0.0, 0.0, 0.0};
+    const Entry en{0.0, 0.0, -1, 0, false};
+    cast_fp32<false, false, SMALL, true>(v, slot, z, z, z, en, V3<bool>{false, false, false}, sk,
+                                         acc, res, &job);
+  }
+}
+
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
 __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
   cast_grid<VAR, TRACE, STATS, OUT64>(a);
@@ -1147,6 +1326,14 @@ template <bool OUT64, bool SMALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CVX_CAST32_WAVES))) void k_cast32(
     CastArgs a) {
   cast_grid<(int)CVX_VARIANT_FP32_REBASED, false, false, OUT64, SMALL>(a);
+}
+
+// The refilling render keeps the ray setup inside its loop; seven
+// wavefronts per SIMD leave it the registers to do so without spills.
+template <bool SMALL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CVX_CAST32R_WAVES))) void k_cast32r(
+    CastArgs a) {
+  cast_grid_refill<SMALL>(a);
 }
 
 // The FP64 caster keeps its direction, reciprocal and eye in registers (they
@@ -1200,13 +1387,22 @@ int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
   if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN && !TRACE && !STATS)
     hipLaunchKernelGGL((k_cast64<TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);
-  else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && !TRACE && !STATS)
-    if (a.small_pools)
+  else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && !TRACE && !STATS && !OUT64) {
+    if (a.item_tiles > 1u) {
+      if (a.small_pools)
+        hipLaunchKernelGGL((k_cast32r<true>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream,
+                           a);
+      else
+        hipLaunchKernelGGL((k_cast32r<false>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream,
+                           a);
+    } else if (a.small_pools) {
       hipLaunchKernelGGL((k_cast32<OUT64, true>), dim3(wgs), dim3(wg_size), lds,
                          (hipStream_t)stream, a);
-    else
+    } else {
       hipLaunchKernelGGL((k_cast32<OUT64, false>), dim3(wgs), dim3(wg_size), lds,
                          (hipStream_t)stream, a);
+    }
+  }
   else
     hipLaunchKernelGGL((k_cast<VAR, TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);

@@ -156,6 +156,11 @@ struct CastArgs {
   uint64_t* stats;
   uint32_t tile_w, tile_h;
   uint32_t small_pools;  // every pool the views read has at most 2^28 nodes
+  // FP32 render with lane refill when item_tiles > 1: a work item is up to
+  // item_tiles tiles of one view, and waiting lanes take its next rays once
+  // refill_min lanes of the wavefront wait
+  uint32_t item_tiles;
+  uint32_t refill_min;
 };
 
 // kernel launchers (cvx_upload.hip, cvx_cast.hip); return a hipError_t value

@@ -99,7 +99,8 @@ class cvx_render_opts(ctypes.Structure):
                 ("wg_size", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
                 ("out_f64", ctypes.c_uint32), ("top_lookup", ctypes.c_uint32),
                 ("single_queue", ctypes.c_uint32), ("per_ray_start", ctypes.c_uint32),
-                ("wide_offsets", ctypes.c_uint32),
+                ("wide_offsets", ctypes.c_uint32), ("rays_per_wave", ctypes.c_uint32),
+                ("refill_min", ctypes.c_uint32),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
@@ -117,7 +118,8 @@ class cvx_tune_result(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_uint32), ("tile_h", ctypes.c_uint32),
                 ("wg_size", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
                 ("ms", ctypes.c_float), ("top_lookup", ctypes.c_uint32),
-                ("single_queue", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("single_queue", ctypes.c_uint32), ("rays_per_wave", ctypes.c_uint32),
+                ("refill_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class CvxError(RuntimeError):
@@ -235,7 +237,7 @@ def cvx_render_noalloc(ctx, views, out_ptr, opts=None):
 
 def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
     """Returns (best cvx_render_opts, list of (tile_w, tile_h, wg_size, workgroups, ms,
-    top_lookup, single_queue))."""
+    top_lookup, single_queue, rays_per_wave, refill_min))."""
     b = base if base is not None else cvx_render_opts()
     best = cvx_render_opts()
     res = (cvx_tune_result * max_results)()
@@ -244,7 +246,8 @@ def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
                                   ctypes.byref(b), int(reps), ctypes.byref(best), res,
                                   int(max_results), ctypes.byref(n)))
     rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms), r.top_lookup,
-             r.single_queue) for r in res[:min(n.value, max_results)]]
+             r.single_queue, r.rays_per_wave, r.refill_min)
+            for r in res[:min(n.value, max_results)]]
     return best, rows
 
 
@@ -359,9 +362,11 @@ def cvx_validate_views(views, descs):
 
 def make_opts(variant="fp32_rebased", tile=(0, 0), workgroups=0, wg_size=0, use_graph=False,
               out_f64=False, trace=None, stats_ptr=0, top_lookup=0, single_queue=0,
-              per_ray_start=0, wide_offsets=0):
+              per_ray_start=0, wide_offsets=0, rays_per_wave=0, refill_min=0):
     o = cvx_render_opts()
     o.wide_offsets = int(wide_offsets)
+    o.rays_per_wave = int(rays_per_wave)
+    o.refill_min = int(refill_min)
     o.top_lookup = int(top_lookup)
     o.single_queue = int(single_queue)
     o.per_ray_start = int(per_ray_start)

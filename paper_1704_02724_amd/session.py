@@ -99,7 +99,7 @@ class Session:
     def autotune(self, views, variant="fp32_rebased", out=None, reps=3, use_graph=True):
         """Times every candidate launch shape (cvx_autotune); returns the fastest as
         render keyword arguments, and the table of (tile_w, tile_h, wg_size,
-        workgroups, ms, top_lookup, single_queue) rows."""
+        workgroups, ms, top_lookup, single_queue, rays_per_wave, refill_min) rows."""
         torch = self.torch
         if out is None:
             out = torch.empty((self.out_pixels(views), 4), dtype=torch.float32, device=self.device)
@@ -110,7 +110,8 @@ class Session:
         self._leave(out)
         tuning = dict(tile=(best.tile_w, best.tile_h), workgroups=best.workgroups,
                       wg_size=best.wg_size, top_lookup=best.top_lookup,
-                      single_queue=best.single_queue)
+                      single_queue=best.single_queue, rays_per_wave=best.rays_per_wave or 64,
+                      refill_min=best.refill_min if best.rays_per_wave > 64 else 0)
         return tuning, rows
 
     def new_stats(self):

@@ -345,6 +345,43 @@ def test_wide_offsets_same_image(sess):
         np.testing.assert_array_equal(img.cpu().numpy(), ref)
 
 
+def test_lane_refill_same_image(sess):
+    """Lane refill (rays_per_wave > 64: finished lanes take the next rays of a
+    work item of several tiles once refill_min lanes wait) runs the same
+    per-ray arithmetic, so images equal one ray per lane bit for bit: views
+    of ragged sizes whose items end mid-view, eyes inside the canvas (shared
+    first leaf) and outside (rays that miss), rays that stop at an opacity,
+    two canvases, eager and graph launches."""
+    from paper_1704_02724_amd import cvx
+    cv0 = trees.random_tree(1, 9, seed=81, max_nodes=60000, leaf_format=LEAF_RGBA8_F16)
+    cv1 = trees.random_tree(2, 6, seed=82, max_nodes=60000, leaf_format=LEAF_RGBA8_F16)
+    sess.upload(0, cv0)
+    sess.upload(1, cv1)
+    rng = np.random.Generator(np.random.PCG64(83))
+    views, off = [], 0
+    for ci, W, H, inside, stop in [(0, 77, 53, True, 1.0), (1, 120, 41, True, 0.7),
+                                   (0, 33, 90, False, 1.0), (1, 64, 64, False, 0.95),
+                                   (0, 9, 7, True, 1.0)]:
+        e = rng.uniform(0.1, 0.9, 3) if inside else rng.uniform(-1.0, 2.0, 3)
+        tgt = rng.uniform(0.3, 0.7, 3)
+        views.append(make_view(e, tgt - e, rng.uniform(0.4, 1.1), W, H, canvas_id=ci,
+                               out_offset_px=off, alpha_stop=stop))
+        off += W * H
+    for tile in ((8, 8), (16, 4), (4, 16)):
+        ref = sess.render(views, "fp32_rebased", tile=tile).cpu().numpy()
+        assert (ref[:, 3] > 0).any() and (ref[:, 3] == 0).any()
+        for rpw, mn in ((128, 32), (256, 1), (512, 48), (1024, 64), (192, 16)):
+            kw = dict(tile=tile, rays_per_wave=rpw, refill_min=mn)
+            np.testing.assert_array_equal(sess.render(views, "fp32_rebased", **kw).cpu().numpy(),
+                                          ref)
+            img = sess.render(views, "fp32_rebased", use_graph=True, wg_size=64, **kw)
+            np.testing.assert_array_equal(img.cpu().numpy(), ref)
+    for bad in (dict(rays_per_wave=100), dict(rays_per_wave=2048), dict(refill_min=65)):
+        with pytest.raises(cvx.CvxError) as e:
+            sess.render(views, "fp32_rebased", **bad)
+        assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+
+
 def test_autotune_picks_a_timed_shape_and_keeps_the_image(sess):
     """cvx_autotune times every candidate launch shape; every candidate renders
     the same image, and the one it returns is the fastest it timed."""
@@ -356,13 +393,21 @@ def test_autotune_picks_a_timed_shape_and_keeps_the_image(sess):
     tuning, rows = sess.autotune(w.views, "fp32_rebased", out=out, reps=2)
     sess.torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), ref)
-    assert len(rows) == 2 * 2 * 4 * 3 * 4
+    assert len(rows) == 2 * 2 * 4 * 3 * 4 + 6
     assert {(r[0], r[1]) for r in rows} == {(8, 8), (16, 4), (4, 16), (32, 2)}
     assert {r[5] for r in rows} == {0, 1} and {r[6] for r in rows} == {0, 1}
     assert all(r[4] > 0.0 for r in rows)
+    # lane refill is timed on the fastest one-ray-per-lane shape
+    plain = [r for r in rows if r[7] == 64]
+    refill = [r for r in rows if r[7] > 64]
+    assert len(plain) == 192 and all(r[8] == 0 for r in plain)
+    shape = min(plain, key=lambda r: r[4])
+    assert {(r[7], r[8]) for r in refill} == {(a, b) for a in (128, 256) for b in (16, 32, 48)}
+    assert all(r[:4] == shape[:4] and r[5:7] == shape[5:7] for r in refill)
     best = min(rows, key=lambda r: r[4])
     assert tuning == dict(tile=(best[0], best[1]), workgroups=best[3], wg_size=best[2],
-                          top_lookup=best[5], single_queue=best[6])
+                          top_lookup=best[5], single_queue=best[6], rays_per_wave=best[7],
+                          refill_min=best[8])
     img = sess.render(w.views, "fp32_rebased", use_graph=True, **tuning)
     np.testing.assert_array_equal(img.cpu().numpy(), ref)
     varr = cvx.make_views(w.views)

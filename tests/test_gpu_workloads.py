@@ -44,7 +44,8 @@ def _sampled(sess, w, ids, variant):
     replay) against the oracle.  The two kernel instances are tied together:
     the rendered pixels equal the traced RGBA bit for bit, and the image of
     the instance that reads pools with 64-bit addresses (the one pools above
-    2^28 nodes take) equals the default one bit for bit."""
+    2^28 nodes take) equals the default one bit for bit, and so does the image
+    with lane refill switched the other way."""
     for i, c in enumerate(w.canvases):
         sess.upload(i, c)
     orc = oracle.render(w.canvases, w.views, ids, max_leaves=ML)
@@ -60,6 +61,12 @@ def _sampled(sess, w, ids, variant):
     np.testing.assert_array_equal(gpu["rgba"], img[offs[vi] + px])
     wide = sess.render(w.views, variant, use_graph=True, wide_offsets=1, **tuning)
     np.testing.assert_array_equal(wide.cpu().numpy(), img)
+    # lane refill (or, when the tuner picked it, one ray per lane) renders the
+    # same image
+    alt = dict(tuning, rays_per_wave=64 if tuning.get("rays_per_wave", 64) > 64 else 256,
+               refill_min=32)
+    other = sess.render(w.views, variant, use_graph=True, **alt)
+    np.testing.assert_array_equal(other.cpu().numpy(), img)
     return cmp, err, orc, gpu
 
 

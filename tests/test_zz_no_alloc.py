@@ -63,7 +63,8 @@ def test_noalloc_equals_render_twice_shrinking(sess):
         np.testing.assert_array_equal(simg, sref)
     # with a tuned launch shape, eye inside the canvas (shared first leaf) or not
     for kw in (dict(tile=(16, 4), wg_size=64, workgroups=37),
-               dict(tile=(4, 16), wg_size=256, single_queue=1, per_ray_start=1)):
+               dict(tile=(4, 16), wg_size=256, single_queue=1, per_ray_start=1),
+               dict(rays_per_wave=256, refill_min=16)):
         for views in (first, second):
             ref, img, _, _ = _both(sess, views, **kw)
             np.testing.assert_array_equal(img, ref)
