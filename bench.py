@@ -516,6 +516,10 @@ def main():
     ap.add_argument("--per-view-steps", type=int, default=-1,
                     help="steps of the one-launch-per-view comparison (default 3 when the "
                          "workload has more than two views; 0 skips it)")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only run the vector-issue probe (lib/probe_valu: wave64 VALU "
+                         "instructions per SIMD per clock for the loop's instruction kinds) "
+                         "and print its JSON")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the device-to-device copy timed as the measured HBM peak "
                          "(also the reference for hardware byte counters); 0 skips it")
@@ -525,6 +529,13 @@ def main():
               "on one GPU; rays are independent, so more GPUs would split the tiles of a "
               "replicated pool", file=sys.stderr)
         sys.exit(2)
+    if args.issue_probe:
+        import subprocess
+        from paper_1704_02724_amd.build import PROBE_PATH
+        r = subprocess.run([PROBE_PATH], capture_output=True, text=True, timeout=120)
+        sys.stderr.write(r.stderr)
+        print(r.stdout.strip(), flush=True)
+        sys.exit(r.returncode)
     extras = [x for x in args.extra.split(",") if x]
     for x in extras:
         if x not in WORKLOADS:

@@ -34,17 +34,32 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB_PATH + ".tmp"
-    cmd = (["hipcc"] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp]
-           + [os.path.join(CSRC, s) for s in SOURCES])
+# The vector-issue probe behind the caster's roofline (a measurement program,
+# not part of the library): lib/probe_valu, run by bench.py --issue-probe.
+PROBE_SRC = os.path.join(CSRC, "probe_valu.hip")
+PROBE_PATH = os.path.join(LIB_DIR, "probe_valu")
+PROBE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _hipcc(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+    return res
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(LIB_DIR, exist_ok=True)
+    tmp = LIB_PATH + ".tmp"
+    res = _hipcc(["hipcc"] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp]
+                 + [os.path.join(CSRC, s) for s in SOURCES])
     if verbose:
         print(res.stderr)
     os.replace(tmp, LIB_PATH)
+    ptmp = PROBE_PATH + ".tmp"
+    _hipcc(["hipcc"] + PROBE_FLAGS + ["-o", ptmp, PROBE_SRC])
+    os.replace(ptmp, PROBE_PATH)
     return LIB_PATH
 
 

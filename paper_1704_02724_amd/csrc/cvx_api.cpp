@@ -415,6 +415,8 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     }
     dv.tan_x = v.tan_half_fov_x;
     dv.tan_y = v.tan_half_fov_y;
+    dv.two_w = 2.0 / (double)v.W;
+    dv.two_h = 2.0 / (double)v.H;
     dv.W = v.W;
     dv.H = v.H;
     dv.out_off = v.out_offset_px;

@@ -94,20 +94,25 @@ __device__ __forceinline__ void record(Sink& sk, uint32_t n, uint32_t I, double 
   }
 }
 
-// FP64 unit direction of pixel (x, y); the exact operation order of the
-// public convention, no contraction.
+// FP64 unit direction of pixel (x, y) in the public convention
+// (normalize(fwd + u right + v up), u and v from the pixel centre), no
+// contraction.  The divisions by the image size are products with the
+// view's 2/W and 2/H (each rounded once) and the normalisation multiplies by
+// one reciprocal of the norm: each component stays within a few FP64 ulp of
+// the convention's division form, far inside the 1e-12 band in which
+// crossings count as ambiguous.
 __device__ __forceinline__ V3<double> ray_dir(const DView& v, uint32_t x, uint32_t y) {
 #pragma clang fp contract(off)
-  double u = (2.0 * ((double)x + 0.5) / (double)v.W - 1.0) * v.tan_x;
-  double w = (1.0 - 2.0 * ((double)y + 0.5) / (double)v.H) * v.tan_y;
+  double u = (((double)x + 0.5) * v.two_w - 1.0) * v.tan_x;
+  double w = (1.0 - ((double)y + 0.5) * v.two_h) * v.tan_y;
   double d[3], n2 = 0.0;
   for (int k = 0; k < 3; ++k) {
     d[k] = v.fwd[k] + u * v.right[k];
     d[k] = d[k] + w * v.up[k];
     n2 += d[k] * d[k];
   }
-  double n = __builtin_sqrt(n2);
-  return V3<double>{d[0] / n, d[1] / n, d[2] / n};
+  const double rn = 1.0 / __builtin_sqrt(n2);
+  return V3<double>{d[0] * rn, d[1] * rn, d[2] * rn};
 }
 
 struct Entry {
@@ -469,11 +474,13 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
     w = 1u << (db - dep);
     const double hd = ldexp(1.0, -(int)dep);
-    // rolled: one FP64 division live at a time
+    // rolled: one FP64 plane live at a time; the plane's parameter uses the
+    // ray's correctly rounded reciprocal direction (a few FP64 ulp, inside
+    // the rebase term of the bound)
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
       const double X = (double)get(c, k) * hd + (get(up, k) ? hd : 0.0);  // exact
-      const double Tk = (X - slot.at(k)) / slot.at(3 + k);
+      const double Tk = (X - slot.at(k)) * slot.at(6 + k);
       set(S0, k, get(tD, k) == 0.0f ? BIGF : (float)ldexp(Tk - te, (int)db));
     }
     Nk = V3<int32_t>{0, 0, 0};
@@ -774,7 +781,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       const int kr = ke < 0 ? 0 : ke;
       const uint32_t cr = get(c, kr);
       const double Xp = (double)(get(up, kr) ? cr : cr + 1u) * ldexp(1.0, -(int)dep);
-      const double te = (Xp - slot.at(kr)) / slot.at(3 + kr);
+      const double te = (Xp - slot.at(kr)) * slot.at(6 + kr);
       for (int k = 0; k < 3; ++k) set(q, k, k == kr ? Xp : slot.at(k) + te * slot.at(3 + k));
       rebase(te);
     }

@@ -101,6 +101,7 @@ struct DView {
   double o[3];          // eye in root-edge units
   double right[3], up[3], fwd[3];
   double tan_x, tan_y;
+  double two_w, two_h;  // 2 / W and 2 / H, rounded once
   uint32_t W, H;
   uint64_t out_off;
   uint64_t first_tile;  // prefix sum of tile counts over the views
