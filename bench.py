@@ -309,9 +309,31 @@ def stroke_bench(sess, cv, seed):
     return out
 
 
-def parity_check(sess, w, ids, img, variant):
+def merged_pieces(gpu, n, pieces):
+    """Whole-ray leaf sequences from a chord-piece trace (rows (ray, piece),
+    ray-major): the pieces concatenated, a leaf cut by a piece boundary
+    counted once."""
+    ids = gpu["leaf_ids"].reshape(n, pieces, -1)
+    cnt = gpu["n_leaves"].reshape(n, pieces).astype(np.int64)
+    out_ids = np.zeros((n, ML), np.uint32)
+    out_n = np.zeros(n, np.uint32)
+    for r in range(n):
+        seq = []
+        for j in range(pieces):
+            part = ids[r, j, :min(int(cnt[r, j]), ML)].tolist()
+            if seq and part and part[0] == seq[-1]:
+                part = part[1:]
+            seq.extend(part)
+        out_n[r] = len(seq)
+        seq = seq[:ML]
+        out_ids[r, :len(seq)] = seq
+    return dict(leaf_ids=out_ids, n_leaves=out_n)
+
+
+def parity_check(sess, w, ids, img, variant, tuning):
     """Leaf sequences and RGBA of `variant` against the oracle on the sampled
-    rays, and the naive canvas-global FP32 caster on the same rays."""
+    rays, and the naive canvas-global FP32 caster on the same rays.  With
+    chord pieces the timed kernel's sequences are the merged piece traces."""
     from oracle import oracle
     views = w.views
     orc = oracle.render(w.canvases, views, ids, max_leaves=ML)
@@ -329,19 +351,33 @@ def parity_check(sess, w, ids, img, variant):
     offs = np.array([v["out_offset_px"] for v in views], np.int64)
     pix = img[offs[vi] + px]
     rgba_err = np.abs(pix.astype(np.float64) - orc["rgba"]).max(axis=1)
-    ok = seq_ok(gpu)
     n = len(ids)
+    P = int(tuning.get("chord_pieces", 1))
+    if P > 1:
+        # the timed kernel splits chords: its sequences are the merged piece
+        # traces; the whole-chord kernel is tied to its trace separately
+        ok = seq_ok(merged_pieces(sess.trace(views, ids, ML, variant, chord_pieces=P), n, P))
+        whole = sess.render(views, variant, use_graph=True,
+                            **dict(tuning, chord_pieces=1)).cpu().numpy()
+        wpix = whole[offs[vi] + px]
+        split_diff = float(np.abs(pix.astype(np.float64) - wpix).max())
+    else:
+        ok = seq_ok(gpu)
+        wpix, split_diff = pix, 0.0
     par = dict(rays=int(n), flagged=int(skip.sum()),
                bit_exact_share=round(float((~skip).mean()), 4),
                seq_mismatch=int((~ok & ~skip).sum()),
                seq_mismatch_flagged=int((~ok & skip).sum()),
+               seq_mismatch_whole_chord=int((~seq_ok(gpu) & ~skip).sum()),
                max_rgba_err=float(rgba_err[~skip].max()),
                max_rgba_err_flagged=float(rgba_err[skip].max()) if skip.any() else 0.0,
-               trace_equals_render=bool(np.array_equal(gpu["rgba"], pix)),
+               trace_equals_render=bool(np.array_equal(gpu["rgba"], wpix)),
+               chord_pieces=P, split_vs_whole_max_diff=split_diff,
                gpu_fp64_exit_rays=int(((gpu["flags"] & 2) != 0).sum()),
                mean_leaves=round(float(orc["n_leaves"].mean()), 1))
-    par["pass"] = (par["seq_mismatch"] == 0 and par["max_rgba_err"] <= 1e-3
-                   and par["trace_equals_render"])
+    par["pass"] = (par["seq_mismatch"] == 0 and par["seq_mismatch_whole_chord"] == 0
+                   and par["max_rgba_err"] <= 1e-3 and par["trace_equals_render"]
+                   and split_diff <= 1e-3)
     naive = sess.trace(views, ids, ML, "fp32_naive")
     nok = seq_ok(naive)
     nerr = np.abs(naive["rgba"].astype(np.float64) - orc["rgba"]).max(axis=1)
@@ -377,12 +413,13 @@ def run_workload(sess, name, args, headline, copy_bps):
         tuning, tune_rows = sess.autotune(views, args.variant, reps=reps)
         log(f"[{name}] autotune {args.variant}: {tuning} in {time.perf_counter() - t:.1f}s; "
             "fastest: " + ", ".join(f"{r[0]}x{r[1]}/wg{r[2]}/{r[3]}/top{r[5]}/q{r[6]}/"
-                                    f"rpw{r[7]}/min{r[8]}: {r[4]:.3f}ms"
+                                    f"rpw{r[7]}/min{r[8]}/pieces{r[9]}: {r[4]:.3f}ms"
                                     for r in sorted(tune_rows, key=lambda r: r[4])[:4]))
-        refill_rows = [r for r in tune_rows if r[7] > 64]
-        if refill_rows:
-            log(f"[{name}] lane refill on the fastest shape: "
-                + ", ".join(f"rpw{r[7]}/min{r[8]}: {r[4]:.3f}ms" for r in refill_rows))
+        plain = [r for r in tune_rows if r[7] == 64 and r[9] == 1]
+        extra = [r for r in tune_rows if r[7] > 64 or r[9] > 1]
+        if extra:
+            log(f"[{name}] on the fastest plain shape ({min(r[4] for r in plain):.3f}ms): "
+                + ", ".join(f"rpw{r[7]}/min{r[8]}/pieces{r[9]}: {r[4]:.3f}ms" for r in extra))
         if args.fp64_steps > 0:
             tuning64, _ = sess.autotune(views, "fp64_plain", reps=1)
             log(f"[{name}] autotune fp64_plain: {tuning64}")
@@ -427,7 +464,7 @@ def run_workload(sess, name, args, headline, copy_bps):
     ids = sample_ids(views, args.parity_sample if headline else args.extra_parity_sample,
                      12345)
     img = out.cpu().numpy()
-    parity, naive, mean_b_oracle = parity_check(sess, w, ids, img, args.variant)
+    parity, naive, mean_b_oracle = parity_check(sess, w, ids, img, args.variant, tuning)
     log(f"[{name}] parity: {parity}")
     log(f"[{name}] naive fp32: {naive}")
 
@@ -441,6 +478,7 @@ def run_workload(sess, name, args, headline, copy_bps):
                            single_queue=int(tuning.get("single_queue", 0)),
                            rays_per_wave=int(tuning.get("rays_per_wave", 64)),
                            refill_min=int(tuning.get("refill_min", 0)),
+                           chord_pieces=int(tuning.get("chord_pieces", 1)),
                            autotuned=not args.no_autotune),
                fp64_plain_mrays=round(fp64, 2) if fp64 else None,
                speedup_vs_fp64_plain=round(value / fp64, 3) if fp64 else None,

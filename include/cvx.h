@@ -166,6 +166,26 @@ typedef struct {
                             (Sec. 6.2: a ray stops at full opacity or at the canvas exit;
                             refilling keeps the other lanes busy).  Same result. */
   uint32_t refill_min;  /* lanes that must wait before they are refilled, 1..64 (0 = 32) */
+  uint32_t chord_pieces; /* FP32_REBASED only, 1 (0 = 1), 2, 4 or 8: the canvas chord [t0, t1]
+                            of every ray of a view that runs to the canvas exit (alpha_stop
+                            >= 1) is cut at t0 + (t1 - t0) (67 j + 1) / (67 chord_pieces)
+                            (not at dyadic fractions, so that no cut lies on a cell plane by
+                            construction) into pieces traced
+                            as separate work items, each compositing its leaves (the leaf
+                            holding a cut contributes the part on each side to each piece)
+                            into a colour and transmittance, merged front to back per pixel
+                            by the associative over operator (C1 + T1 C2, T1 T2) (Sec. 6.2
+                            composites front to back; the operator is that compositing
+                            regrouped).  Several short work items per ray shorten the end of
+                            a launch that holds few rays per lane.  Images agree with the
+                            whole chord's within the FP32 length precision of the traversal
+                            (the pieces rebase at their cuts; not bit for bit).  With trace,
+                            the buffers hold n * chord_pieces rows, ray-major, (ray, piece)
+                            each, rgba = (the piece's premultiplied colour, its
+                            transmittance); rows past a view's piece count are empty.  Not
+                            with rays_per_wave > 64, with trace and stats together, or in
+                            cvx_render_noalloc (merging needs a buffer the context
+                            allocates); stats renders run whole chords. */
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;
@@ -242,7 +262,7 @@ typedef struct {
   uint32_t single_queue;   /* as in cvx_render_opts */
   uint32_t rays_per_wave;  /* as in cvx_render_opts (64: no refill) */
   uint32_t refill_min;     /* as in cvx_render_opts (0 when rays_per_wave is 64) */
-  uint32_t reserved;
+  uint32_t chord_pieces;   /* as in cvx_render_opts (1: whole chords) */
 } cvx_tune_result;
 
 /* Autotuner of the batch scheduler's launch shape: renders `views` exactly as
@@ -252,12 +272,15 @@ typedef struct {
  * (on, off) and work queues (per XCD, single), one untimed warm-up
  * then `reps` renders timed with HIP events on the context stream.  For
  * FP32_REBASED the fastest of those shapes is then timed with lane refill,
- * rays_per_wave 128 and 256 with refill_min 16, 32 and 48, which are
- * candidates like the others.  Writes
+ * rays_per_wave 128 and 256 with refill_min 16, 32 and 48, and with
+ * chord_pieces 2, 4 and 8, which are candidates like the others (the split
+ * renders agree with the others within the FP32 length precision, not bit
+ * for bit).  Writes
  * base with the fastest shape filled in to *best and, when results is not
  * NULL, up to max_results timed candidates in the order tried (the count
  * tried goes to *n_results when not NULL).  out_dev receives the renders
- * (identical for every candidate).  base->trace and base->stats must be
+ * (identical for every candidate but the chord-piece ones, which agree
+ * within the FP32 length precision).  base->trace and base->stats must be
  * NULL; reps in [1, 1000].  Synchronous; an error from a candidate's render
  * is returned as is. */
 int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,

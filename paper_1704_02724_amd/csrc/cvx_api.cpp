@@ -19,14 +19,17 @@ using cvx::DevCanvas;
 using cvx::DView;
 
 struct GraphKey {
-  uint32_t variant = ~0u, tw = 0, th = 0, wgs = 0, wg = 0, item_tiles = 1, refill_min = 0;
+  uint32_t variant = ~0u, tw = 0, th = 0, wgs = 0, wg = 0, item_tiles = 1, refill_min = 0,
+           pieces = 1;
   bool trace = false, stats = false, out64 = false, small = false, per_ray_start = false;
   const void* out = nullptr;
   const void* stats_ptr = nullptr;
   const void* views = nullptr;
+  const void* split_tmp = nullptr;
   bool operator==(const GraphKey& o) const {
     return variant == o.variant && tw == o.tw && th == o.th && wgs == o.wgs && wg == o.wg &&
-           item_tiles == o.item_tiles && refill_min == o.refill_min &&
+           item_tiles == o.item_tiles && refill_min == o.refill_min && pieces == o.pieces &&
+           split_tmp == o.split_tmp &&
            trace == o.trace && stats == o.stats && out64 == o.out64 && small == o.small &&
            per_ray_start == o.per_ray_start &&
            out == o.out && stats_ptr == o.stats_ptr && views == o.views;
@@ -47,6 +50,9 @@ struct cvx_ctx {
   CastHeader* h_hdr = nullptr;  // pinned staging
   hipEvent_t staged{};
   bool staged_pending = false;
+  // chord pieces of split renders: (colour, T) per pixel and piece
+  void* d_split = nullptr;
+  size_t split_cap = 0;
   // cvx_render_noalloc: the library's device scratch array on this device
   // (a CastHeader, then the view table) and a pinned host copy of it
   void* d_scratch = nullptr;
@@ -183,6 +189,7 @@ void cvx_destroy(cvx_ctx* ctx) {
   for (auto& c : ctx->canvases) free_canvas(c);
   if (ctx->d_views) (void)hipFree(ctx->d_views);
   if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
+  if (ctx->d_split) (void)hipFree(ctx->d_split);
   if (ctx->h_views) (void)hipHostFree(ctx->h_views);
   if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
   if (ctx->staged) (void)hipEventDestroy(ctx->staged);
@@ -320,6 +327,8 @@ namespace {
 struct RenderPlan {
   uint32_t tw = 8, th = 8, wg = 256, wgs = 0;
   uint32_t item_tiles = 1, refill_min = 32;  // lane refill of the FP32 render (item_tiles > 1)
+  uint32_t pieces = 1;  // chord pieces per ray of the FP32 render or trace (views that run to
+                        // the canvas exit; 1: unsplit)
 };
 
 // Checks the options and views of a render call (nothing is launched on an
@@ -349,6 +358,17 @@ int render_check(cvx_ctx* ctx, const cvx_view* views, int n_views, const void* o
   const bool refill = o.variant == CVX_VARIANT_FP32_REBASED && !o.trace && !o.stats && rpw > 64u;
   p.item_tiles = refill ? rpw / 64u : 1u;
   p.refill_min = refill ? (o.refill_min ? o.refill_min : 32u) : 0u;
+  const uint32_t pieces = o.chord_pieces ? o.chord_pieces : 1u;
+  if (pieces != 1 && pieces != 2 && pieces != 4 && pieces != 8)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "chord_pieces must be 1, 2, 4 or 8");
+  if (pieces > 1 && o.variant != CVX_VARIANT_FP32_REBASED)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "chord_pieces needs the FP32_REBASED variant");
+  if (pieces > 1 && rpw > 64u)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "chord_pieces and rays_per_wave > 64 do not combine");
+  if (pieces > 1 && o.stats && o.trace)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "chord_pieces with trace takes no stats");
+  // stats renders count the unsplit traversal (the same per-ray counts)
+  p.pieces = o.stats ? 1u : pieces;
   if (o.out_f64 && o.variant != CVX_VARIANT_FP64_PLAIN)
     return fail(ctx, CVX_ERR_INVALID_ARG, "out_f64 needs the FP64_PLAIN variant");
   const cvx_trace* tr = o.trace;
@@ -388,6 +408,8 @@ struct RenderStage {
   hipEvent_t staged;  // recorded after the copies; the host staging is reused only after it
   bool* staged_pending;
   bool contiguous;
+  bool split_ok;           // a split render may use the context's piece buffer
+  const char* split_why;   // the error otherwise
 };
 
 // Fills the staged views and header, copies them to the device and launches
@@ -427,6 +449,10 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     // item_tiles tiles (an item never straddles views)
     dv.first_tile = first;
     first += ((uint64_t)dv.tiles_x * tiles_y + p.item_tiles - 1) / p.item_tiles;
+    // chord pieces only where rays run to the canvas exit (an opacity stop
+    // ends a ray part-way, which a later piece cannot know)
+    dv.pieces = (p.pieces > 1 && !(v.alpha_stop < 1.0f)) ? p.pieces : 1u;
+    if (!tr) first += ((uint64_t)dv.tiles_x * tiles_y) * (dv.pieces - 1u);  // items: tile x piece
     uint64_t cap = 3ull * c.desc.R * (1ull << std::min<uint32_t>(c.depth, 40)) + 16;
     dv.max_steps = (uint32_t)std::min<uint64_t>(cap, 1ull << 22);
     dv.n_nodes = (uint32_t)c.n_nodes;
@@ -436,8 +462,10 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     dv.start_ok = 0;  // set on the device by k_view_starts
   }
   CastHeader& H = *st.h_hdr;
-  H.total_work = tr ? (tr->n + 63) / 64 : first;
-  H.n_rays = tr ? tr->n : 0;
+  // trace rows: one per ray, or per (ray, piece) with chord pieces
+  const uint64_t rows = tr ? tr->n * p.pieces : 0;
+  H.total_work = tr ? (rows + 63) / 64 : first;
+  H.n_rays = rows;
   H.n_views = (uint32_t)n_views;
   H.n_queues = o.single_queue ? 1u : cvx::CVX_NQ;
   for (auto& q : H.queue) q.next = 0;
@@ -463,6 +491,7 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   a.tile_h = p.th;
   a.item_tiles = p.item_tiles;
   a.refill_min = p.refill_min;
+  a.pieces = p.pieces;
   a.small_pools = o.wide_offsets ? 0u : 1u;
   for (int i = 0; i < n_views; ++i)
     if (ctx->canvases[views[i].canvas_id].n_nodes > (1ull << 28)) a.small_pools = 0;
@@ -479,6 +508,30 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   }
   const bool stats = o.stats != nullptr;
   const uint32_t shared_start = o.per_ray_start ? 0u : 1u;
+  // a split render writes its pieces to the context's buffer, merged after
+  bool merge = false;
+  if (!tr && p.pieces > 1) {
+    uint64_t px_end = 0;
+    for (int i = 0; i < n_views; ++i)
+      if (st.h_views[i].pieces > 1)
+        px_end = std::max<uint64_t>(px_end, views[i].out_offset_px +
+                                                (uint64_t)views[i].W * views[i].H);
+    if (px_end) {
+      if (!st.split_ok) return fail(ctx, CVX_ERR_INVALID_ARG, st.split_why);
+      const size_t need = (size_t)px_end * p.pieces * 16;
+      if (need > ctx->split_cap) {
+        CVX_HIP(hipStreamSynchronize(ctx->stream));
+        if (ctx->d_split) (void)hipFree(ctx->d_split);
+        ctx->d_split = nullptr;
+        ctx->split_cap = 0;
+        CVX_HIP(hipMalloc(&ctx->d_split, need));
+        ctx->split_cap = need;
+        drop_graph(ctx);
+      }
+      merge = true;
+    }
+  }
+  a.split_tmp = merge ? ctx->d_split : nullptr;
   if (!o.use_graph || tr) {
     int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_view_starts");
@@ -487,6 +540,11 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     le = cvx::launch_cast(ctx->stream, o.variant, tr != nullptr, stats, o.out_f64 != 0, a, p.wgs,
                           p.wg);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_cast");
+    if (merge) {
+      le = cvx::launch_merge_pieces(ctx->stream, st.d_views, st.d_hdr, (uint32_t)n_views,
+                                    ctx->d_split, out_dev, p.pieces);
+      if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_merge_pieces");
+    }
     return CVX_OK;
   }
   GraphKey key;
@@ -497,6 +555,8 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   key.wg = p.wg;
   key.item_tiles = p.item_tiles;
   key.refill_min = p.refill_min;
+  key.pieces = p.pieces;
+  key.split_tmp = a.split_tmp;
   key.trace = false;
   key.stats = stats;
   key.out64 = o.out_f64 != 0;
@@ -512,6 +572,9 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     if (le == hipSuccess) le = cvx::launch_reset(ctx->stream, st.d_hdr);
     if (le == hipSuccess)
       le = cvx::launch_cast(ctx->stream, o.variant, false, stats, o.out_f64 != 0, a, p.wgs, p.wg);
+    if (le == hipSuccess && merge)
+      le = cvx::launch_merge_pieces(ctx->stream, st.d_views, st.d_hdr, (uint32_t)n_views,
+                                    ctx->d_split, out_dev, p.pieces);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
     if (le != hipSuccess) {
@@ -564,7 +627,7 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     drop_graph(ctx);
   }
   const RenderStage st{ctx->h_views, ctx->h_hdr,  ctx->d_views,           ctx->d_hdr,
-                       ctx->staged,  &ctx->staged_pending, false};
+                       ctx->staged,  &ctx->staged_pending, false,  true, ""};
   return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 
@@ -596,7 +659,10 @@ int cvx_render_noalloc(cvx_ctx* ctx, const cvx_view* views, int n_views, void* o
   const RenderStage st{(DView*)(h + sizeof(CastHeader)), (CastHeader*)h,
                        (DView*)(d + sizeof(CastHeader)), (CastHeader*)d,
                        ctx->scratch_staged,              &ctx->scratch_pending,
-                       true};
+                       true,
+                       false,
+                       "cvx_render_noalloc renders whole chords (chord_pieces 1): merging "
+                       "pieces needs a buffer"};
   return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 
@@ -1407,7 +1473,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
       x.single_queue = o.single_queue;
       x.rays_per_wave = o.rays_per_wave ? o.rays_per_wave : 64u;
       x.refill_min = o.rays_per_wave > 64u ? o.refill_min : 0u;
-      x.reserved = 0;
+      x.chord_pieces = o.chord_pieces ? o.chord_pieces : 1u;
     }
     ++count;
     if (!have || ms < best_ms) {
@@ -1431,6 +1497,7 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         o.single_queue = sq;
         o.rays_per_wave = 0;
         o.refill_min = 0;
+        o.chord_pieces = 0;
         float ms = 0.0f;
         rc = time_candidate(o, ms);
         if (rc != CVX_OK) break;
@@ -1456,6 +1523,17 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
         if (rc != CVX_OK) break;
         record(o, ms);
       }
+    }
+    // chord pieces on the same shape
+    static const uint32_t kPieces[] = {2, 4, 8};
+    for (uint32_t pc : kPieces) {
+      if (rc != CVX_OK) break;
+      cvx_render_opts o = shape;
+      o.chord_pieces = pc;
+      float ms = 0.0f;
+      rc = time_candidate(o, ms);
+      if (rc != CVX_OK) break;
+      record(o, ms);
     }
   }
   (void)hipEventDestroy(e0);

@@ -72,6 +72,7 @@ struct Acc {
 
 struct Out {
   double rgba[4];
+  double T;        // FP32_REBASED: the transmittance (a chord piece's, when split)
   double end[3];   // trace mode: the exit point of the last leaf as the variant computed it
   uint32_t flags;
   uint32_t n;
@@ -288,8 +289,8 @@ __device__ __forceinline__ void locate_top(const DView& v, const V3<uint32_t>& C
 // by the caller.
 __device__ __forceinline__ void start_leaf(const DView& v, const V3<double>& q, const V3<bool>& up,
                                            uint32_t& I, uint32_t& dep, V3<uint32_t>& c,
-                                           uint4& r) {
-  if (v.start_ok) {
+                                           uint4& r, bool shared = true) {
+  if (shared && v.start_ok) {
     I = v.start_node;
     dep = v.start_dep;
     c = V3<uint32_t>{v.start_c[0], v.start_c[1], v.start_c[2]};
@@ -432,11 +433,19 @@ struct RefillJob {
 // en, up describe it) or, REFILL = true, the rays a RefillJob hands out one
 // after another, each written to its pixel when it ends.  The per-ray
 // arithmetic is the same in both, so both give the same pixels.
-template <bool TRACE, bool STATS, bool SMALL, bool REFILL = false>
+// SPLIT = true: the ray's chord is cut at ray parameter t_end (the end of a
+// chord piece; infinity for the last piece): the leaf holding t_end
+// contributes only the part before it, decided like an exit (certified, else
+// in FP64 from the exact exit plane), and the piece ends there; a piece that
+// does not start at the canvas entry locates its first leaf from its start
+// point (shared_start = false: not through the view's shared eye leaf).
+template <bool TRACE, bool STATS, bool SMALL, bool REFILL = false, bool SPLIT = false>
 __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& o_in,
                           const V3<double>& d_in, const V3<double>& inv_in, const Entry& en_in,
                           const V3<bool>& up_in, Sink sk, Acc& acc, Out& out,
-                          const RefillJob* job = nullptr) {
+                          const RefillJob* job = nullptr, double t_end = 0.0,
+                          bool shared_start = true) {
+  static_assert(!(REFILL && SPLIT), "chord pieces are traced one per lane");
   const void* rec = v.rec;
   const void* payp = v.pay;
   const bool use_stop = v.alpha_stop < 1.0f;
@@ -462,6 +471,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   uint32_t ub = 0;
   uint32_t step = 0;
   uint32_t end_Nn = 0, end_nc = 0, end_dep = 0;  // the move the ray ended on
+  // SPLIT: s-value of the piece's end and its error bound (BIGF: no end)
+  float s_end = BIGF, e_end = 0.0f;
   // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
   // current cell I is descended first when it is refined.
   auto rebase = [&](double te) __attribute__((always_inline)) {
@@ -488,6 +499,13 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     const float beta = ldexpf(tR, (int)db - 50);
     e_ent = beta;
     betac = beta * BETA_C;
+    if constexpr (SPLIT) {
+      // (t_end - te) 2^db rounded to FP32 (2^-24 relative) after an FP64
+      // difference within beta
+      const bool has_end = t_end < __builtin_inf();
+      s_end = has_end ? (float)ldexp(t_end - te, (int)db) : BIGF;
+      e_end = has_end ? beta + __builtin_fabsf(s_end) * 0x1p-23f : 0.0f;
+    }
     if (STATS) acc.rebase++;
   };
   // ray start: the FP64 entry point, the first leaf and the first frame (Rd =
@@ -511,7 +529,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       set(q, k, qk < 0.0 ? 0.0 : (qk > Rd ? Rd : qk));
     }
     dep = 0;
-    start_leaf(v, q, up, I, dep, c, r);
+    start_leaf(v, q, up, I, dep, c, r, shared_start);
     if (STATS) acc.descent += dep;
     pay = make_uint2(0u, 0u);
     db = 0;
@@ -542,6 +560,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     out.rgba[1] = C.y * k255;
     out.rgba[2] = C.z * k255;
     out.rgba[3] = 1.0f - T;
+    out.T = T;
     out.n = n_rec;
     out.steps = step + 1;
     if (STATS) acc.leaves += n_rec;
@@ -702,12 +721,32 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         const double t = te_last + ldexp((double)Sx, -(int)db);
         for (int k = 0; k < 3; ++k) out.end[k] = slot.at(k) + t * slot.at(3 + k);
       }
+      // SPLIT: does the piece end inside this leaf?  Certainly when the exit
+      // lies beyond the end by more than both bounds, certainly not when it
+      // lies before it by as much; otherwise the exit plane's exact FP64
+      // parameter decides (an exit exactly at the end belongs to this piece,
+      // and the next piece starts in the next leaf)
+      bool cut = false;
+      float Sl = Sx;  // where this leaf's segment ends
+      if constexpr (SPLIT) {
+        const float eb_end = ex + e_end;
+        if (Sx + eb_end >= s_end) {
+          if (Sx - eb_end > s_end) {
+            cut = true;
+          } else {
+            const double hd = ldexp(1.0, -(int)dep);
+            const double X = (double)get(c, kx) * hd + (get(up, kx) ? hd : 0.0);
+            cut = (X - slot.at(kx)) * slot.at(6 + kx) > t_end;
+          }
+        }
+        Sl = cut ? s_end : Sx;
+      }
       // length precision guard: rebase once the bound on this segment's
       // length exceeds 2^-10 of the leaf edge (w = 2^(db - dep) base cells);
       // for a positive float, x > 2^n exactly when its bits exceed those of 2^n
       const float eseg = ex + e_ent;
       need64 = need64 || __builtin_bit_cast(uint32_t, eseg) > ((db - dep + 117u) << 23);
-      float len = ldexpf(Sx - s_ent, (int)dep - (int)db);
+      float len = ldexpf(Sl - s_ent, (int)dep - (int)db);
       len = len > 0.0f ? len : 0.0f;
       // composite; every visited leaf is recorded: for a ray outside the face
       // band the exact segment is positive even when it rounds to 0 here
@@ -719,6 +758,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       T = Tn;
       if (TRACE) record(sk, n_rec, I, len);
       ++n_rec;
+      if constexpr (SPLIT) {
+        if (cut) break;  // the piece ends inside this leaf (no move, no flags)
+      }
       // ---- neighbour across the exit face: sibling, next root or G_3 link
       const bool mz = !mx & !my;
       const uint32_t ck = mx ? c.x : (my ? c.y : c.z);
@@ -1136,12 +1178,22 @@ __device__ void cast_local(const DView& v, const V3<double>& d, const Entry& en,
   if (STATS) acc.leaves += n_rec;
 }
 
-template <int VAR, bool TRACE, bool STATS, bool SMALL = false>
-__device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out) {
+// One ray, or with SPLIT its chord piece `piece` of `pieces`: the canvas
+// chord [t0, t1] cut at t0 + (t1 - t0) f_j, f_j = (67 j + 1) / (67 pieces)
+// (the same FP64 expression for the end of piece j - 1 and the start of
+// piece j).  A cut at j / pieces would fall exactly on a cell plane whenever
+// the chord runs between opposite canvas faces of one axis (the midpoint of
+// [0, R] is a plane), where the end test of one piece and the point location
+// of the next could round to different sides; with the factor 67 (no root
+// array side has it) the cut points are not dyadic.
+template <int VAR, bool TRACE, bool STATS, bool SMALL = false, bool SPLIT = false>
+__device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc& acc, Out& out,
+                         uint32_t piece = 0, uint32_t pieces = 1) {
   const RaySlot slot{(lds_f64*)(s_ray + threadIdx.x), blockDim.x};
   const V3<double> d = ray_dir(v, px, py);
   const V3<double> o{v.o[0], v.o[1], v.o[2]};
   out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
+  out.T = 1.0;
   out.flags = 0;
   out.n = 0;
   out.steps = 0;
@@ -1151,7 +1203,21 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   const Entry en = canvas_entry(o, d, inv, (double)v.R);
   if (!en.hit) return;
   const V3<bool> up{d.x > 0.0, d.y > 0.0, d.z > 0.0};
-  if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
+  if constexpr (SPLIT) {
+    static_assert(VAR == (int)CVX_VARIANT_FP32_REBASED, "chord pieces: FP32_REBASED only");
+    const double span = en.t1 - en.t0;
+    const double den = 67.0 * (double)pieces;
+    Entry ep = en;
+    if (piece > 0) {  // starts inside the chord, on no face
+      ep.t0 = en.t0 + span * (double)(67u * piece + 1u) / den;
+      ep.kin = -1;
+    }
+    const double t_end = piece + 1 < pieces
+                             ? en.t0 + span * (double)(67u * (piece + 1u) + 1u) / den
+                             : __builtin_inf();
+    cast_fp32<TRACE, STATS, SMALL, false, true>(v, slot, o, d, inv, ep, up, sk, acc, out, nullptr,
+                                                t_end, piece == 0);
+  } else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED) {
     cast_fp32<TRACE, STATS, SMALL>(v, slot, o, d, inv, en, up, sk, acc, out);
   } else if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN) {
     cast_fp64<TRACE, STATS>(v, d, inv, en, up, sk, acc, out);
@@ -1177,7 +1243,11 @@ __device__ __forceinline__ DView uniform_view(const DView& v) {
   return u;
 }
 
-template <int VAR, bool TRACE, bool STATS, bool OUT64, bool SMALL = false>
+// SPLIT: every view with pieces > 1 has pieces work items per tile (tile
+// t, piece j at t * pieces + j); each piece writes its colour and
+// transmittance to a.split_tmp[pixel * a.pieces + j] for k_merge_pieces.  In
+// trace mode the rows are (ray, piece) pairs, ray-major, a.pieces per ray.
+template <int VAR, bool TRACE, bool STATS, bool OUT64, bool SMALL = false, bool SPLIT = false>
 __device__ __forceinline__ void cast_grid(const CastArgs& a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t total = a.hdr->total_work;
@@ -1208,14 +1278,23 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
         if (a.views[mid].first_tile <= (uint64_t)w) lo = mid; else hi = mid - 1;
       }
       const DView v = uniform_view(a.views[lo]);
-      const uint64_t t = (uint64_t)w - v.first_tile;
+      uint64_t t = (uint64_t)w - v.first_tile;
+      uint32_t piece = 0;
+      if constexpr (SPLIT) {
+        piece = (uint32_t)(t % v.pieces);
+        t /= v.pieces;
+      }
       const uint32_t tx = (uint32_t)(t % v.tiles_x), ty = (uint32_t)(t / v.tiles_x);
       const uint32_t x = tx * a.tile_w + lane % a.tile_w, y = ty * a.tile_h + lane / a.tile_w;
       if (x < v.W && y < v.H) {
         Sink sk{nullptr, nullptr, nullptr, 0};
-        cast_ray<VAR, false, STATS, SMALL>(v, x, y, sk, acc, res);
+        cast_ray<VAR, false, STATS, SMALL, SPLIT>(v, x, y, sk, acc, res, piece, v.pieces);
         const uint64_t pix = v.out_off + (uint64_t)y * v.W + x;
-        if constexpr (OUT64) {
+        if (SPLIT && v.pieces > 1) {
+          ((float4*)a.split_tmp)[pix * a.pieces + piece] =
+              make_float4((float)res.rgba[0], (float)res.rgba[1], (float)res.rgba[2],
+                          (float)res.T);
+        } else if constexpr (OUT64) {
           double2* o2 = (double2*)a.out + 2 * pix;
           o2[0] = make_double2(res.rgba[0], res.rgba[1]);
           o2[1] = make_double2(res.rgba[2], res.rgba[3]);
@@ -1227,7 +1306,10 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
     } else {
       const uint64_t ri = (uint64_t)w * 64u + lane;
       if (ri < a.hdr->n_rays) {
-        const uint64_t id = a.ray_ids[ri];
+        // SPLIT: row ri is piece ri % a.pieces of ray ri / a.pieces
+        const uint64_t ray = SPLIT ? ri / a.pieces : ri;
+        const uint32_t piece = SPLIT ? (uint32_t)(ri % a.pieces) : 0u;
+        const uint64_t id = a.ray_ids[ray];
         const uint32_t vi = (uint32_t)(id >> 32), pix = (uint32_t)(id & 0xffffffffu);
         a.n_leaves[ri] = 0;
         a.flags[ri] = CVX_RAYFLAG_BAD_LINK;
@@ -1237,13 +1319,24 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
             Sink sk{a.leaf_ids + ri * a.max_leaves,
                     a.local_len ? a.local_len + ri * a.max_leaves : nullptr,
                     a.local_len64 ? a.local_len64 + ri * a.max_leaves : nullptr, a.max_leaves};
-            cast_ray<VAR, TRACE, STATS, SMALL>(v, pix % v.W, pix / v.W, sk, acc, res);
+            if (!SPLIT || piece < v.pieces) {
+              cast_ray<VAR, TRACE, STATS, SMALL, SPLIT>(v, pix % v.W, pix / v.W, sk, acc, res,
+                                                         piece, v.pieces);
+            } else {  // an unsplit view: its rays have one piece, the others are empty
+              res.rgba[0] = res.rgba[1] = res.rgba[2] = res.rgba[3] = 0.0;
+              res.T = 1.0;
+              res.flags = 0;
+              res.n = 0;
+              res.end[0] = res.end[1] = res.end[2] = 0.0;
+            }
             a.n_leaves[ri] = res.n;
             a.flags[ri] = res.flags;
             if (a.end_point)
               for (int k = 0; k < 3; ++k) a.end_point[3 * ri + k] = res.end[k];
-            ((float4*)a.trace_rgba)[ri] = make_float4((float)res.rgba[0], (float)res.rgba[1],
-                                                      (float)res.rgba[2], (float)res.rgba[3]);
+            // with pieces, a row holds its piece's colour and transmittance
+            ((float4*)a.trace_rgba)[ri] =
+                make_float4((float)res.rgba[0], (float)res.rgba[1], (float)res.rgba[2],
+                            SPLIT ? (float)res.T : (float)res.rgba[3]);
           }
         }
       }
@@ -1320,9 +1413,9 @@ __device__ __forceinline__ void cast_grid_refill(const CastArgs& a) {
   }
 }
 
-template <int VAR, bool TRACE, bool STATS, bool OUT64>
+template <int VAR, bool TRACE, bool STATS, bool OUT64, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
-  cast_grid<VAR, TRACE, STATS, OUT64>(a);
+  cast_grid<VAR, TRACE, STATS, OUT64, false, SPLIT>(a);
 }
 
 // Render-mode entry points with an occupancy target (trace and stats
@@ -1333,6 +1426,38 @@ template <bool OUT64, bool SMALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CVX_CAST32_WAVES))) void k_cast32(
     CastArgs a) {
   cast_grid<(int)CVX_VARIANT_FP32_REBASED, false, false, OUT64, SMALL>(a);
+}
+
+// The FP32 render of chord pieces (views with pieces > 1; the others as
+// k_cast32), with the same occupancy target.
+template <bool SMALL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CVX_CAST32_WAVES))) void k_cast32s(
+    CastArgs a) {
+  cast_grid<(int)CVX_VARIANT_FP32_REBASED, false, false, false, SMALL, true>(a);
+}
+
+// Front-to-back merge of the chord pieces of every pixel of the split views
+// (blockIdx.y = view): C = C_0 + T_0 C_1 + T_0 T_1 C_2 + ..., the pixel's
+// alpha 1 - T_0 T_1 ...  (the associative over operator on (C, T) pairs).
+__global__ void k_merge_pieces(const DView* views, const CastHeader* hdr, const float4* tmp,
+                               float4* out, uint32_t stride) {
+  if (blockIdx.y >= hdr->n_views) return;  // the count of this call (graphs replay)
+  const DView& v = views[blockIdx.y];
+  if (v.pieces <= 1u) return;
+  const uint64_t n = (uint64_t)v.W * v.H;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t pix = v.out_off + i;
+    float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
+    for (uint32_t j = 0; j < v.pieces; ++j) {
+      const float4 q = tmp[pix * stride + j];
+      cr = __builtin_fmaf(T, q.x, cr);
+      cg = __builtin_fmaf(T, q.y, cg);
+      cb = __builtin_fmaf(T, q.z, cb);
+      T *= q.w;
+    }
+    out[pix] = make_float4(cr, cg, cb, 1.0f - T);
+  }
 }
 
 // The refilling render keeps the ray setup inside its loop; seven
@@ -1394,8 +1519,22 @@ int launch_t(void* stream, const CastArgs& a, uint32_t wgs, uint32_t wg_size) {
   if constexpr (VAR == (int)CVX_VARIANT_FP64_PLAIN && !TRACE && !STATS)
     hipLaunchKernelGGL((k_cast64<TRACE, STATS, OUT64>), dim3(wgs), dim3(wg_size), lds,
                        (hipStream_t)stream, a);
-  else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && !TRACE && !STATS && !OUT64) {
-    if (a.item_tiles > 1u) {
+  else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && TRACE && !STATS && !OUT64) {
+    if (a.pieces > 1u)
+      hipLaunchKernelGGL((k_cast<VAR, true, false, false, true>), dim3(wgs), dim3(wg_size), lds,
+                         (hipStream_t)stream, a);
+    else
+      hipLaunchKernelGGL((k_cast<VAR, true, false, false>), dim3(wgs), dim3(wg_size), lds,
+                         (hipStream_t)stream, a);
+  } else if constexpr (VAR == (int)CVX_VARIANT_FP32_REBASED && !TRACE && !STATS && !OUT64) {
+    if (a.pieces > 1u) {
+      if (a.small_pools)
+        hipLaunchKernelGGL((k_cast32s<true>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream,
+                           a);
+      else
+        hipLaunchKernelGGL((k_cast32s<false>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream,
+                           a);
+    } else if (a.item_tiles > 1u) {
       if (a.small_pools)
         hipLaunchKernelGGL((k_cast32r<true>), dim3(wgs), dim3(wg_size), lds, (hipStream_t)stream,
                            a);
@@ -1455,6 +1594,13 @@ int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out
 int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable) {
   hipLaunchKernelGGL(k_view_starts, dim3((CVX_MAX_VIEWS + 63u) / 64u), dim3(64), 0,
                      (hipStream_t)stream, views, hdr, enable);
+  return (int)hipGetLastError();
+}
+
+int launch_merge_pieces(void* stream, const DView* views, const CastHeader* hdr, uint32_t n_views,
+                        const void* tmp, void* out, uint32_t stride) {
+  hipLaunchKernelGGL(k_merge_pieces, dim3(256, n_views), dim3(256), 0, (hipStream_t)stream, views,
+                     hdr, (const float4*)tmp, (float4*)out, stride);
   return (int)hipGetLastError();
 }
 

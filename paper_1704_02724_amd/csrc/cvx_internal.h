@@ -115,6 +115,8 @@ struct DView {
   // device before the cast; start_ok = 0: each ray locates its first leaf
   uint32_t start_ok, start_node, start_dep;
   uint32_t start_c[3];  // its integer coordinates at start_dep
+  uint32_t pieces;      // chord pieces per ray (1: unsplit)
+  uint32_t pad0;
 };
 
 // Work queues: the work items (tiles or 64-ray chunks) are split into
@@ -162,6 +164,12 @@ struct CastArgs {
   // refill_min lanes of the wavefront wait
   uint32_t item_tiles;
   uint32_t refill_min;
+  // FP32 render or trace of chord pieces when pieces > 1: a view with
+  // pieces > 1 splits each ray's chord into that many consecutive pieces,
+  // traced as separate work items; render pieces write (colour, T) to
+  // split_tmp[pixel * pieces + piece] for the merge
+  uint32_t pieces;
+  void* split_tmp;
 };
 
 // kernel launchers (cvx_upload.hip, cvx_cast.hip); return a hipError_t value
@@ -184,6 +192,9 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
 int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out_f64,
                 const CastArgs& a, uint32_t workgroups, uint32_t wg_size);
 int launch_reset(void* stream, CastHeader* hdr);
+// the front-to-back merge of chord pieces into out (views with pieces > 1)
+int launch_merge_pieces(void* stream, const DView* views, const CastHeader* hdr, uint32_t n_views,
+                        const void* tmp, void* out, uint32_t stride);
 // Scratch of the allocation-free render entry point: a CastHeader followed by
 // CVX_NOALLOC_MAX_VIEWS view records, in a fixed device array of
 // cvx_cast.hip.  scratch_address returns its address on the current device

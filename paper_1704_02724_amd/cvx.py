@@ -100,7 +100,7 @@ class cvx_render_opts(ctypes.Structure):
                 ("out_f64", ctypes.c_uint32), ("top_lookup", ctypes.c_uint32),
                 ("single_queue", ctypes.c_uint32), ("per_ray_start", ctypes.c_uint32),
                 ("wide_offsets", ctypes.c_uint32), ("rays_per_wave", ctypes.c_uint32),
-                ("refill_min", ctypes.c_uint32),
+                ("refill_min", ctypes.c_uint32), ("chord_pieces", ctypes.c_uint32),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
@@ -119,7 +119,7 @@ class cvx_tune_result(ctypes.Structure):
                 ("wg_size", ctypes.c_uint32), ("workgroups", ctypes.c_uint32),
                 ("ms", ctypes.c_float), ("top_lookup", ctypes.c_uint32),
                 ("single_queue", ctypes.c_uint32), ("rays_per_wave", ctypes.c_uint32),
-                ("refill_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("refill_min", ctypes.c_uint32), ("chord_pieces", ctypes.c_uint32)]
 
 
 class CvxError(RuntimeError):
@@ -237,7 +237,7 @@ def cvx_render_noalloc(ctx, views, out_ptr, opts=None):
 
 def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
     """Returns (best cvx_render_opts, list of (tile_w, tile_h, wg_size, workgroups, ms,
-    top_lookup, single_queue, rays_per_wave, refill_min))."""
+    top_lookup, single_queue, rays_per_wave, refill_min, chord_pieces))."""
     b = base if base is not None else cvx_render_opts()
     best = cvx_render_opts()
     res = (cvx_tune_result * max_results)()
@@ -246,7 +246,7 @@ def cvx_autotune(ctx, views, out_ptr, base=None, reps=3, max_results=256):
                                   ctypes.byref(b), int(reps), ctypes.byref(best), res,
                                   int(max_results), ctypes.byref(n)))
     rows = [(r.tile_w, r.tile_h, r.wg_size, r.workgroups, float(r.ms), r.top_lookup,
-             r.single_queue, r.rays_per_wave, r.refill_min)
+             r.single_queue, r.rays_per_wave, r.refill_min, r.chord_pieces)
             for r in res[:min(n.value, max_results)]]
     return best, rows
 
@@ -362,8 +362,10 @@ def cvx_validate_views(views, descs):
 
 def make_opts(variant="fp32_rebased", tile=(0, 0), workgroups=0, wg_size=0, use_graph=False,
               out_f64=False, trace=None, stats_ptr=0, top_lookup=0, single_queue=0,
-              per_ray_start=0, wide_offsets=0, rays_per_wave=0, refill_min=0):
+              per_ray_start=0, wide_offsets=0, rays_per_wave=0, refill_min=0,
+              chord_pieces=0):
     o = cvx_render_opts()
+    o.chord_pieces = int(chord_pieces)
     o.wide_offsets = int(wide_offsets)
     o.rays_per_wave = int(rays_per_wave)
     o.refill_min = int(refill_min)

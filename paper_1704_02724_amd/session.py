@@ -99,7 +99,8 @@ class Session:
     def autotune(self, views, variant="fp32_rebased", out=None, reps=3, use_graph=True):
         """Times every candidate launch shape (cvx_autotune); returns the fastest as
         render keyword arguments, and the table of (tile_w, tile_h, wg_size,
-        workgroups, ms, top_lookup, single_queue, rays_per_wave, refill_min) rows."""
+        workgroups, ms, top_lookup, single_queue, rays_per_wave, refill_min,
+        chord_pieces) rows."""
         torch = self.torch
         if out is None:
             out = torch.empty((self.out_pixels(views), 4), dtype=torch.float32, device=self.device)
@@ -111,18 +112,22 @@ class Session:
         tuning = dict(tile=(best.tile_w, best.tile_h), workgroups=best.workgroups,
                       wg_size=best.wg_size, top_lookup=best.top_lookup,
                       single_queue=best.single_queue, rays_per_wave=best.rays_per_wave or 64,
-                      refill_min=best.refill_min if best.rays_per_wave > 64 else 0)
+                      refill_min=best.refill_min if best.rays_per_wave > 64 else 0,
+                      chord_pieces=best.chord_pieces or 1)
         return tuning, rows
 
     def new_stats(self):
         return self.torch.zeros(cvx.CVX_STAT_COUNT, dtype=self.torch.int64, device=self.device)
 
     def trace(self, views, ray_ids, max_leaves=256, variant="fp32_rebased", len64=False,
-              end_point=False):
+              end_point=False, chord_pieces=1):
+        """Visited leaves, lengths, flags and RGBA of the listed rays; with
+        chord_pieces > 1 one row per (ray, piece), ray-major, rgba = (the
+        piece's colour, its transmittance)."""
         torch = self.torch
         ids = torch.from_numpy(np.ascontiguousarray(ray_ids, dtype=np.uint64).view(np.int64))
         ids = ids.to(self.device)
-        n = len(ray_ids)
+        n = len(ray_ids) * max(1, int(chord_pieces))
         leaf_ids = torch.zeros((n, max(max_leaves, 1)), dtype=torch.int32, device=self.device)
         llen = torch.zeros((n, max(max_leaves, 1)),
                            dtype=torch.float64 if len64 else torch.float32, device=self.device)
@@ -131,7 +136,7 @@ class Session:
         rgba = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
         end = torch.zeros((n, 3), dtype=torch.float64, device=self.device) if end_point else None
         tr = cvx.cvx_trace()
-        tr.n = n
+        tr.n = len(ray_ids)
         tr.ray_ids = ids.data_ptr()
         tr.max_leaves = max_leaves
         tr.leaf_ids = leaf_ids.data_ptr()
@@ -142,7 +147,7 @@ class Session:
         tr.rgba = rgba.data_ptr()
         tr.end_point = end.data_ptr() if end is not None else None
         varr = cvx.make_views(views)
-        opts = cvx.make_opts(variant, trace=tr)
+        opts = cvx.make_opts(variant, trace=tr, chord_pieces=chord_pieces)
         self._enter()
         cvx.cvx_render(self.ctx, varr, 0, opts)
         self._leave(ids, leaf_ids, llen, nl, fl, rgba, *([end] if end is not None else []))

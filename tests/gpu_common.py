@@ -52,3 +52,34 @@ def rgba_err(a, b, mask=None):
     if mask is not None:
         e = e[mask]
     return float(e.max()) if len(e) else 0.0
+
+
+def merge_piece_traces(gpu, n, pieces, max_leaves):
+    """Whole-ray traces from a chord-piece trace (rows (ray, piece), ray-major):
+    the pieces' leaf sequences concatenated, a leaf cut by a piece boundary
+    (the last of one piece and the first of the next) counted once; flags
+    or-ed; RGBA merged front to back from the pieces' (colour, transmittance)."""
+    ids = gpu["leaf_ids"].reshape(n, pieces, -1)
+    cnt = gpu["n_leaves"].reshape(n, pieces).astype(np.int64)
+    out_ids = np.zeros((n, max_leaves), np.uint32)
+    out_n = np.zeros(n, np.uint32)
+    for r in range(n):
+        seq = []
+        for j in range(pieces):
+            part = ids[r, j, :min(int(cnt[r, j]), max_leaves)].tolist()
+            if seq and part and part[0] == seq[-1]:
+                part = part[1:]
+            seq.extend(part)
+        out_n[r] = len(seq)
+        seq = seq[:max_leaves]
+        out_ids[r, :len(seq)] = seq
+    rgba = gpu["rgba"].reshape(n, pieces, 4).astype(np.float64)
+    c = np.zeros((n, 3))
+    t = np.ones(n)
+    for j in range(pieces):
+        c += t[:, None] * rgba[:, j, :3]
+        t *= rgba[:, j, 3]
+    return dict(leaf_ids=out_ids, n_leaves=out_n,
+                flags=np.bitwise_or.reduce(gpu["flags"].reshape(n, pieces), axis=1),
+                rgba=np.concatenate([c, (1.0 - t)[:, None]], axis=1),
+                local_len=np.zeros((n, max_leaves), np.float32))

@@ -14,11 +14,16 @@ LIB_DIR = os.path.join(ROOT, "paper_1704_02724_amd", "lib")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
+HDR = os.path.join(ROOT, "include", "cvx.h")
+
+
 def build_c_check():
-    """Compile the program with gcc (host code only) if missing or stale."""
+    """Compile the program with gcc (host code only) if missing or older than
+    its source or the header (the structures it passes are the header's)."""
     if not os.path.exists(os.path.join(LIB_DIR, "libcvx.so")):
         pytest.skip("libcvx.so is not built")
-    if os.path.exists(OUT) and os.path.getmtime(OUT) >= os.path.getmtime(SRC):
+    if os.path.exists(OUT) and os.path.getmtime(OUT) >= max(os.path.getmtime(SRC),
+                                                            os.path.getmtime(HDR)):
         return OUT
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     cmd = ["gcc", "-std=c99", "-O1", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",

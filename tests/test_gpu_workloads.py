@@ -11,7 +11,7 @@ import pytest
 from canvasgen import configs
 from oracle import oracle
 
-from gpu_common import compare_traces, rgba_err, sample_ray_ids
+from gpu_common import compare_traces, merge_piece_traces, rgba_err, sample_ray_ids
 
 pytestmark = pytest.mark.gpu
 ML = 1024
@@ -38,14 +38,16 @@ def depth30():
     return configs.depth30()
 
 
-def _sampled(sess, w, ids, variant):
+def _sampled(sess, w, ids, variant, pieces=None):
     """Leaf sequences of the trace kernel against the oracle, and RGBA of the
     image rendered as the benchmark times it (autotuned launch shape, graph
-    replay) against the oracle.  The two kernel instances are tied together:
-    the rendered pixels equal the traced RGBA bit for bit, and the image of
-    the instance that reads pools with 64-bit addresses (the one pools above
-    2^28 nodes take) equals the default one bit for bit, and so does the image
-    with lane refill switched the other way."""
+    replay) against the oracle.  The kernel instances are tied together: the
+    whole-chord render's pixels equal the traced RGBA bit for bit, the image
+    of the instance that reads pools with 64-bit addresses (the one pools
+    above 2^28 nodes take) equals the default one bit for bit, and so does
+    the image with lane refill switched the other way.  When the tuner (or
+    `pieces`) splits chords, the split traces' merged sequences are compared
+    with the oracle too and the split image with the whole-chord one."""
     for i, c in enumerate(w.canvases):
         sess.upload(i, c)
     orc = oracle.render(w.canvases, w.views, ids, max_leaves=ML)
@@ -53,20 +55,34 @@ def _sampled(sess, w, ids, variant):
     assert np.all((gpu["flags"] & 0x5) == 0)
     cmp = compare_traces(orc, gpu, ML, len_atol=1e-3)
     tuning, _ = sess.autotune(w.views, variant, reps=1)
+    if pieces is not None:
+        tuning = dict(tuning, chord_pieces=pieces, rays_per_wave=64, refill_min=0)
     img = sess.render(w.views, variant, use_graph=True, **tuning).cpu().numpy()
     vi = (ids >> np.uint64(32)).astype(np.int64)
     px = (ids & np.uint64(0xFFFFFFFF)).astype(np.int64)
     offs = np.array([v["out_offset_px"] for v in w.views], np.int64)
     err = rgba_err(img[offs[vi] + px], orc["rgba"], cmp["ok_mask"])
-    np.testing.assert_array_equal(gpu["rgba"], img[offs[vi] + px])
+    whole_tuning = dict(tuning, chord_pieces=1)
+    whole = (img if tuning.get("chord_pieces", 1) == 1 else
+             sess.render(w.views, variant, use_graph=True, **whole_tuning).cpu().numpy())
+    np.testing.assert_array_equal(gpu["rgba"], whole[offs[vi] + px])
     wide = sess.render(w.views, variant, use_graph=True, wide_offsets=1, **tuning)
     np.testing.assert_array_equal(wide.cpu().numpy(), img)
     # lane refill (or, when the tuner picked it, one ray per lane) renders the
     # same image
-    alt = dict(tuning, rays_per_wave=64 if tuning.get("rays_per_wave", 64) > 64 else 256,
+    alt = dict(whole_tuning, rays_per_wave=64 if tuning.get("rays_per_wave", 64) > 64 else 256,
                refill_min=32)
     other = sess.render(w.views, variant, use_graph=True, **alt)
-    np.testing.assert_array_equal(other.cpu().numpy(), img)
+    np.testing.assert_array_equal(other.cpu().numpy(), whole)
+    P = tuning.get("chord_pieces", 1)
+    if P > 1:
+        assert np.abs(img - whole).max() <= 1e-3
+        split = merge_piece_traces(sess.trace(w.views, ids, ML, variant, chord_pieces=P),
+                                   len(ids), P, ML)
+        assert np.all((split["flags"] & 0x5) == 0)
+        scmp = compare_traces(orc, split, ML)
+        assert scmp["seq_mismatch"] == 0, scmp
+        assert rgba_err(split["rgba"], img[offs[vi] + px]) <= 1e-6
     return cmp, err, orc, gpu
 
 
@@ -117,6 +133,19 @@ def test_depth30_sampled(sess, depth30, variant):
           f"mean leaves {orc['n_leaves'].mean():.1f}, max {orc['n_leaves'].max()}")
     assert cmp["seq_mismatch"] == 0, cmp
     assert err <= 1e-3
+
+
+def test_depth30_chord_pieces_sampled(sess, depth30):
+    """The depth-30 view rendered with chord pieces (its launch holds about
+    two rays per lane, so its end is set by the longest rays; pieces shorten
+    them): merged leaf sequences of the split traces against the oracle,
+    RGBA of the split render against the oracle and the whole-chord render."""
+    ids = sample_ray_ids(depth30.views, 16384, 3033)
+    for P in (2, 4):
+        cmp, err, orc, _ = _sampled(sess, depth30, ids, "fp32_rebased", pieces=P)
+        print(f"depth30 pieces={P}: {cmp['n']} rays, flagged {cmp['flagged']}, rgba err {err:.3g}")
+        assert cmp["seq_mismatch"] == 0, cmp
+        assert err <= 1e-3
 
 
 def test_depth30_k10_sampled(sess):

@@ -83,10 +83,11 @@ def test_noalloc_limits(sess):
         cvx.cvx_render_noalloc(sess.ctx, varr, out.data_ptr(), cvx.make_opts())
     assert e.value.code == cvx.CVX_ERR_INVALID_ARG
     assert "CVX_NOALLOC_MAX_VIEWS" in str(e.value)
-    with pytest.raises(cvx.CvxError) as e:
-        cvx.cvx_render_noalloc(sess.ctx, cvx.make_views(too_many[:2]), out.data_ptr(),
-                               cvx.make_opts(use_graph=True))
-    assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+    for bad in (dict(use_graph=True), dict(chord_pieces=2)):
+        with pytest.raises(cvx.CvxError) as e:
+            cvx.cvx_render_noalloc(sess.ctx, cvx.make_views(too_many[:2]), out.data_ptr(),
+                                   cvx.make_opts(**bad))
+        assert e.value.code == cvx.CVX_ERR_INVALID_ARG
     # the largest allowed view set renders as cvx_render does
     most = too_many[:cvx.CVX_NOALLOC_MAX_VIEWS]
     ref, img, _, _ = _both(sess, most)
