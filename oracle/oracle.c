@@ -130,6 +130,58 @@ void orc_ray_dir(const orc_view* v, uint32_t x, uint32_t y, double d[3]) {
   for (int k = 0; k < 3; ++k) d[k] = d[k] / n;
 }
 
+/* Canvas entry and exit of the ray o + t d (root units) by the slab test
+ * against [0, R]^3 (the chord of Sec. 6.1's full-precision start point).
+ * Returns 0 for a ray parallel to an axis and outside the canvas on it; else
+ * 1 with the slab parameters tin (-inf if none), tout, the axis kin and side
+ * of the entry face (kin = -1 when no slab bounds t from below). */
+static int canvas_slabs(const double o[3], const double d[3], double Rd, double* tin_out,
+                        double* tout_out, int* kin_out, int* side_out) {
+  double tin = -INFINITY, tout = INFINITY;
+  int kin = -1, sin_side = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] != 0.0) {
+      double ta = (0.0 - o[k]) / d[k], tb = (Rd - o[k]) / d[k];
+      double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+      if (lo > tin) {
+        tin = lo;
+        kin = k;
+        sin_side = d[k] > 0.0 ? 0 : 1;
+      }
+      if (hi < tout) tout = hi;
+    } else if (o[k] < 0.0 || o[k] > Rd) {
+      return 0; /* parallel and outside: miss */
+    }
+  }
+  *tin_out = tin;
+  *tout_out = tout;
+  *kin_out = kin;
+  *side_out = sin_side;
+  return 1;
+}
+
+/* Pixel directions and canvas chords of the listed pixels of view v over
+ * canvas cv (the set-up of orc_trace, for the precision experiment's exact
+ * rays): d_out (3 per ray) the unit direction, t_out (2 per ray) the chord
+ * [t0, t1] in root-edge units along d, t0 = max(entry, 0); t0 = t1 = 0 for a
+ * miss. */
+void orc_ray_setup(const orc_canvas* cv, const orc_view* v, const uint64_t* px, uint64_t n,
+                   double* d_out, double* t_out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    double* d = d_out + 3 * i;
+    orc_ray_dir(v, (uint32_t)(px[i] % v->W), (uint32_t)(px[i] / v->W), d);
+    double o[3], tin, tout;
+    int kin, side;
+    for (int k = 0; k < 3; ++k) o[k] = (v->eye[k] - cv->origin[k]) / cv->root_edge;
+    t_out[2 * i] = t_out[2 * i + 1] = 0.0;
+    if (!canvas_slabs(o, d, (double)cv->R, &tin, &tout, &kin, &side)) continue;
+    double t0 = tin > 0.0 ? tin : 0.0;
+    if (!(t0 < tout)) continue;
+    t_out[2 * i] = t0;
+    t_out[2 * i + 1] = tout;
+  }
+}
+
 /* Locate the leaf containing point q (root units) by descending from the root
  * array.  On a mid-plane the child on the side the ray moves into is taken. */
 static int locate(const orc_canvas* cv, const double q[3], const double d[3], uint32_t* node,
@@ -182,22 +234,9 @@ int orc_trace(const orc_canvas* cv, const double o_world[3], const double d[3], 
   for (int k = 0; k < 3; ++k) o[k] = (o_world[k] - cv->origin[k]) / cv->root_edge;
 
   /* canvas entry: slab test against [0, R]^3 */
-  double tin = -INFINITY, tout = INFINITY;
-  int kin = -1, sin_side = 0;
-  for (int k = 0; k < 3; ++k) {
-    if (d[k] != 0.0) {
-      double ta = (0.0 - o[k]) / d[k], tb = (Rd - o[k]) / d[k];
-      double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
-      if (lo > tin) {
-        tin = lo;
-        kin = k;
-        sin_side = d[k] > 0.0 ? 0 : 1;
-      }
-      if (hi < tout) tout = hi;
-    } else if (o[k] < 0.0 || o[k] > Rd) {
-      return 0; /* parallel and outside: miss */
-    }
-  }
+  double tin, tout;
+  int kin, sin_side;
+  if (!canvas_slabs(o, d, Rd, &tin, &tout, &kin, &sin_side)) return 0; /* parallel, outside */
   double t0 = tin > 0.0 ? tin : 0.0, t1 = tout;
   if (!(t0 < t1)) return 0;
   res->chord = t1 - t0;

@@ -66,6 +66,8 @@ def _load():
                                    vp, vp, ctypes.c_int]
         lib.orc_render.restype = ctypes.c_int
         lib.orc_ray_dir.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp]
+        lib.orc_ray_setup.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp]
+        lib.orc_ray_setup.restype = None
         lib.orc_half_to_double.argtypes = [ctypes.c_uint16]
         lib.orc_half_to_double.restype = ctypes.c_double
         _lib = lib
@@ -103,6 +105,20 @@ def ray_dir(view, x, y):
     d = np.zeros(3)
     _load().orc_ray_dir(ctypes.byref(_view_struct(view)), x, y, d.ctypes.data)
     return d
+
+
+def ray_setup(canvas, view, px):
+    """Unit directions (n, 3) and canvas chords t0, t1 (n each, root-edge units
+    along d from the eye; 0, 0 for a miss) of pixels px (y*W + x) of a view:
+    the oracle's own ray set-up."""
+    px = np.ascontiguousarray(px, dtype=np.uint64)
+    d = np.zeros((len(px), 3))
+    t = np.zeros((len(px), 2))
+    c = _canvas_struct(canvas)
+    v = _view_struct(view)
+    _load().orc_ray_setup(ctypes.byref(c), ctypes.byref(v), px.ctypes.data, len(px),
+                          d.ctypes.data, t.ctypes.data)
+    return d, t[:, 0], t[:, 1]
 
 
 def half_to_double(h: int) -> float:

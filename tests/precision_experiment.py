@@ -1,17 +1,18 @@
 """The precision experiment of Sec. 6.3: per-pixel ray-angle error, cells
 crossed and error against ray length, for each traversal variant.
 
-For every pixel the caster reports (trace mode) the exit point of the last
-leaf as the variant computed it.  The exact ray is the pixel's FP64 ray (the
-same pixel convention as the kernels: row 0 at the top, pixel centres,
-d = normalize(fwd + u right + v up)); the angle error is the angle between
-(end point - eye) and d, the along-ray error the difference between the end
-point's distance along d and the exact canvas exit, over the chord length L.
-The paper's stated worst case for its cell-local scheme is an angle of
+Test infrastructure (the analysis of trace-mode output; the library does not
+use it).  For every pixel the caster reports (trace mode) the exit point of
+the last leaf as the variant computed it.  The exact ray is the oracle's
+FP64 ray of that pixel (its direction and canvas chord, oracle.ray_setup);
+the angle error is the angle between (end point - eye) and that direction,
+the along-ray error the difference between the end point's distance along it
+and the exact canvas exit, over the chord length L.  The paper's stated
+worst case for its cell-local scheme is an angle of
 asin(sqrt(2) (e0 / L + 7.5 eps)) with eps = 2^-23 (e0 = start-point error);
 for the half-precision traversal eps = 2^-10.
 
-    python -m paper_1704_02724_amd.precision --workload depth24
+    python tests/precision_experiment.py --workload depth24
 prints one JSON summary (binned by L and by cells crossed).
 """
 from __future__ import annotations
@@ -19,9 +20,15 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 
 import numpy as np
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from oracle import oracle  # noqa: E402
 
 EPS32 = 2.0 ** -23
 EPS16 = 2.0 ** -10
@@ -30,32 +37,6 @@ EPS16 = 2.0 ** -10
 def paper_bound_deg(eps):
     """The worst-case ray angle of Sec. 6.3 with no start-point error."""
     return math.degrees(math.asin(math.sqrt(2) * 7.5 * eps))
-
-
-def pixel_rays(view, ids):
-    """FP64 eye (canvas units) and unit directions of pixels ids of a view."""
-    W, H = view["W"], view["H"]
-    x = (ids % W).astype(np.float64)
-    y = (ids // W).astype(np.float64)
-    u = (2.0 * (x + 0.5) / W - 1.0) * view["tan_x"]
-    v = (1.0 - 2.0 * (y + 0.5) / H) * view["tan_y"]
-    fwd, right, up = (np.asarray(view[k], np.float64) for k in ("fwd", "right", "up"))
-    d = fwd[None, :] + u[:, None] * right[None, :]
-    d = d + v[:, None] * up[None, :]
-    d = d / np.sqrt((d * d).sum(1))[:, None]
-    return d
-
-
-def canvas_chord(o, d, R):
-    """Slab test against [0, R]^3: (t0, t1) per ray, t0 >= 0; t1 < t0 for a miss."""
-    with np.errstate(divide="ignore", invalid="ignore"):
-        ta = (0.0 - o[None, :]) / d
-        tb = (R - o[None, :]) / d
-    lo = np.where(d != 0, np.minimum(ta, tb), -np.inf)
-    hi = np.where(d != 0, np.maximum(ta, tb), np.inf)
-    t0 = np.maximum(lo.max(1), 0.0)
-    t1 = hi.min(1)
-    return t0, t1
 
 
 def measure(sess, canvases, views, variant, max_rays=None, seed=0):
@@ -69,8 +50,7 @@ def measure(sess, canvases, views, variant, max_rays=None, seed=0):
             px = np.sort(rng.choice(n, max_rays // len(views), replace=False))
         cv = canvases[v["canvas_id"]]
         o = (np.asarray(v["eye"], np.float64) - np.asarray(cv.origin)) / cv.root_edge
-        d = pixel_rays(v, px)
-        t0, t1 = canvas_chord(o, d, cv.R)
+        d, t0, t1 = oracle.ray_setup(cv, v, px)
         ids = (np.uint64(vi) << np.uint64(32)) | px.astype(np.uint64)
         tr = sess.trace(views, ids, 1, variant, end_point=True)
         e = tr["end_point"] - o[None, :]
@@ -120,7 +100,7 @@ def main():
     ap.add_argument("--max-rays", type=int, default=0)
     args = ap.parse_args()
     from canvasgen import configs
-    from .session import Session
+    from paper_1704_02724_amd.session import Session
     w = {"depth24": configs.depth24, "depth30": configs.depth30}[args.workload]()
     sess = Session(0)
     for i, c in enumerate(w.canvases):

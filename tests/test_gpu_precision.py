@@ -33,7 +33,7 @@ def sess():
 
 @pytest.mark.parametrize("name", ["depth24", "depth30"])
 def test_ray_angle_errors(sess, name):
-    from paper_1704_02724_amd import precision
+    import precision_experiment as precision
     w = getattr(configs, name)()
     for i, c in enumerate(w.canvases):
         sess.upload(i, c)

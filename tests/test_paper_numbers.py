@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-from paper_1704_02724_amd import precision
+import precision_experiment as precision
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                       "paper_precision_numbers.txt")
