@@ -186,6 +186,11 @@ typedef struct {
                             with rays_per_wave > 64, with trace and stats together, or in
                             cvx_render_noalloc (merging needs a buffer the context
                             allocates); stats renders run whole chords. */
+  const void* cast_events; /* optional, eager launches only (use_graph = 0): a pointer to two
+                            hipEvent_t created by the caller, recorded on the context stream
+                            right before and right after the cast kernel, so that the
+                            kernel's own duration can be read (the call also stages the
+                            views and locates shared first leaves before it) */
   const cvx_trace* trace; /* non-NULL: trace mode (views' out_offset_px unused) */
   uint64_t* stats;      /* optional device array of CVX_STAT_COUNT u64 counters (added to) */
 } cvx_render_opts;

@@ -42,12 +42,12 @@ struct cvx_ctx {
   int n_cu = 256;
   std::string err;
   DevCanvas canvases[CVX_MAX_CANVASES];
-  DView* d_views = nullptr;
-  size_t views_cap = 0;
-  CastHeader* d_hdr = nullptr;
-  DView* h_views = nullptr;  // pinned staging
-  size_t h_cap = 0;
-  CastHeader* h_hdr = nullptr;  // pinned staging
+  // a render call's header and view table, staged in one pinned host block
+  // and copied by one transfer into one device block: CastHeader, then
+  // stage_cap view records
+  void* d_stage = nullptr;
+  void* h_stage = nullptr;
+  size_t stage_cap = 0;
   hipEvent_t staged{};
   bool staged_pending = false;
   // chord pieces of split renders: (colour, T) per pixel and piece
@@ -164,8 +164,10 @@ int cvx_create(cvx_ctx** out, int hip_device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, hip_device);
   if (e == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
-  if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_hdr, sizeof(CastHeader));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_hdr, sizeof(CastHeader), 0);
+  const size_t stage0 = sizeof(CastHeader) + 64 * sizeof(DView);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_stage, stage0);
+  if (e == hipSuccess) e = hipHostMalloc(&ctx->h_stage, stage0, 0);
+  if (e == hipSuccess) ctx->stage_cap = 64;
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
   // the allocation-free render path: the address of this device's scratch
   // array (looked up once per device, with the device current) and the
@@ -187,11 +189,9 @@ void cvx_destroy(cvx_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   drop_graph(ctx);
   for (auto& c : ctx->canvases) free_canvas(c);
-  if (ctx->d_views) (void)hipFree(ctx->d_views);
-  if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
+  if (ctx->d_stage) (void)hipFree(ctx->d_stage);
   if (ctx->d_split) (void)hipFree(ctx->d_split);
-  if (ctx->h_views) (void)hipHostFree(ctx->h_views);
-  if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->staged) (void)hipEventDestroy(ctx->staged);
   if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
   if (ctx->scratch_staged) (void)hipEventDestroy(ctx->scratch_staged);
@@ -381,6 +381,8 @@ int render_check(cvx_ctx* ctx, const cvx_view* views, int n_views, const void* o
   }
   if (o.use_graph && !ctx->stream)
     return fail(ctx, CVX_ERR_INVALID_ARG, "use_graph needs a non-null stream");
+  if (o.cast_events && o.use_graph)
+    return fail(ctx, CVX_ERR_INVALID_ARG, "cast_events are recorded by eager launches only");
 
   const cvx_canvas_desc* descs[CVX_MAX_CANVASES];
   for (int i = 0; i < CVX_MAX_CANVASES; ++i)
@@ -397,17 +399,16 @@ int render_check(cvx_ctx* ctx, const cvx_view* views, int n_views, const void* o
   return CVX_OK;
 }
 
-// Where a render call stages its view table and header: host copies (pinned)
-// and their device destinations.  With `contiguous`, h_views follows h_hdr
-// and d_views follows d_hdr, and one copy moves both.
+// Where a render call stages its header and view table: a pinned host block
+// and its device destination, each a CastHeader followed by the views, so
+// that one copy moves both.
 struct RenderStage {
   DView* h_views;
   CastHeader* h_hdr;
   DView* d_views;
   CastHeader* d_hdr;
-  hipEvent_t staged;  // recorded after the copies; the host staging is reused only after it
+  hipEvent_t staged;  // recorded after the copy; the host staging is reused only after it
   bool* staged_pending;
-  bool contiguous;
   bool split_ok;           // a split render may use the context's piece buffer
   const char* split_why;   // the error otherwise
 };
@@ -470,15 +471,9 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   H.n_queues = o.single_queue ? 1u : cvx::CVX_NQ;
   for (auto& q : H.queue) q.next = 0;
   if (H.total_work >= (1ull << 32)) return fail(ctx, CVX_ERR_INVALID_ARG, "too much work in one call");
-  if (st.contiguous) {
-    CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader) + sizeof(DView) * n_views,
-                           hipMemcpyHostToDevice, ctx->stream));
-  } else {
-    CVX_HIP(hipMemcpyAsync(st.d_views, st.h_views, sizeof(DView) * n_views,
-                           hipMemcpyHostToDevice, ctx->stream));
-    CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader), hipMemcpyHostToDevice,
-                           ctx->stream));
-  }
+  // one transfer; it also zeroes the queue heads for this call
+  CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader) + sizeof(DView) * n_views,
+                         hipMemcpyHostToDevice, ctx->stream));
   CVX_HIP(hipEventRecord(st.staged, ctx->stream));
   *st.staged_pending = true;
 
@@ -535,11 +530,12 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   if (!o.use_graph || tr) {
     int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_view_starts");
-    le = cvx::launch_reset(ctx->stream, st.d_hdr);
-    if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_reset");
+    const hipEvent_t* ev = (const hipEvent_t*)o.cast_events;
+    if (ev) CVX_HIP(hipEventRecord(ev[0], ctx->stream));
     le = cvx::launch_cast(ctx->stream, o.variant, tr != nullptr, stats, o.out_f64 != 0, a, p.wgs,
                           p.wg);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_cast");
+    if (ev) CVX_HIP(hipEventRecord(ev[1], ctx->stream));
     if (merge) {
       le = cvx::launch_merge_pieces(ctx->stream, st.d_views, st.d_hdr, (uint32_t)n_views,
                                     ctx->d_split, out_dev, p.pieces);
@@ -569,7 +565,6 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     drop_graph(ctx);
     CVX_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
-    if (le == hipSuccess) le = cvx::launch_reset(ctx->stream, st.d_hdr);
     if (le == hipSuccess)
       le = cvx::launch_cast(ctx->stream, o.variant, false, stats, o.out_f64 != 0, a, p.wgs, p.wg);
     if (le == hipSuccess && merge)
@@ -609,25 +604,24 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
     CVX_HIP(hipEventSynchronize(ctx->staged));
     ctx->staged_pending = false;
   }
-  if ((size_t)n_views > ctx->h_cap) {
-    if (ctx->h_views) (void)hipHostFree(ctx->h_views);
-    ctx->h_views = nullptr;
-    ctx->h_cap = 0;
-    CVX_HIP(hipHostMalloc((void**)&ctx->h_views, sizeof(DView) * n_views, 0));
-    ctx->h_cap = n_views;
-  }
-  if ((size_t)n_views > ctx->views_cap) {
+  if ((size_t)n_views > ctx->stage_cap) {
     CVX_HIP(hipStreamSynchronize(ctx->stream));
-    if (ctx->d_views) (void)hipFree(ctx->d_views);
-    ctx->d_views = nullptr;
-    ctx->views_cap = 0;
-    size_t cap = std::max<size_t>(64, n_views);
-    CVX_HIP(hipMalloc((void**)&ctx->d_views, sizeof(DView) * cap));
-    ctx->views_cap = cap;
+    if (ctx->d_stage) (void)hipFree(ctx->d_stage);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    ctx->d_stage = ctx->h_stage = nullptr;
+    ctx->stage_cap = 0;
+    const size_t bytes = sizeof(CastHeader) + sizeof(DView) * (size_t)n_views;
+    CVX_HIP(hipMalloc(&ctx->d_stage, bytes));
+    CVX_HIP(hipHostMalloc(&ctx->h_stage, bytes, 0));
+    ctx->stage_cap = (size_t)n_views;
     drop_graph(ctx);
   }
-  const RenderStage st{ctx->h_views, ctx->h_hdr,  ctx->d_views,           ctx->d_hdr,
-                       ctx->staged,  &ctx->staged_pending, false,  true, ""};
+  uint8_t* h = (uint8_t*)ctx->h_stage;
+  uint8_t* d = (uint8_t*)ctx->d_stage;
+  const RenderStage st{(DView*)(h + sizeof(CastHeader)), (CastHeader*)h,
+                       (DView*)(d + sizeof(CastHeader)), (CastHeader*)d,
+                       ctx->staged,                      &ctx->staged_pending,
+                       true,                             ""};
   return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 
@@ -659,7 +653,6 @@ int cvx_render_noalloc(cvx_ctx* ctx, const cvx_view* views, int n_views, void* o
   const RenderStage st{(DView*)(h + sizeof(CastHeader)), (CastHeader*)h,
                        (DView*)(d + sizeof(CastHeader)), (CastHeader*)d,
                        ctx->scratch_staged,              &ctx->scratch_pending,
-                       true,
                        false,
                        "cvx_render_noalloc renders whole chords (chord_pieces 1): merging "
                        "pieces needs a buffer"};

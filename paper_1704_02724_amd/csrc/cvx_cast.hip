@@ -1479,9 +1479,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
 // One thread per view: the leaf holding the eye, when every ray of the view
 // starts there (eye strictly inside the canvas and off every plane of the
 // deepest grid: the slab test then gives t0 = 0 and the start point is the
-// eye itself for every direction).
-__global__ void k_view_starts(DView* views, const CastHeader* hdr, uint32_t enable) {
+// eye itself for every direction).  The first CVX_NQ threads also clear the
+// work-queue heads (the staged header arrives with them at zero; a cleared
+// head keeps a replayed launch safe on its own).
+__global__ void k_view_starts(DView* views, CastHeader* hdr, uint32_t enable) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < CVX_NQ) hdr->queue[i].next = 0u;
   if (i >= hdr->n_views) return;  // the count of this call (a graph replays the launch)
   DView& v = views[i];
   v.start_ok = 0u;
@@ -1507,10 +1510,6 @@ __global__ void k_view_starts(DView* views, const CastHeader* hdr, uint32_t enab
   v.start_c[1] = c.y;
   v.start_c[2] = c.z;
   v.start_ok = 1u;
-}
-
-__global__ void k_reset(CastHeader* hdr) {
-  if (blockIdx.x == 0 && threadIdx.x < CVX_NQ) hdr->queue[threadIdx.x].next = 0u;
 }
 
 template <int VAR, bool TRACE, bool STATS, bool OUT64>
@@ -1591,7 +1590,7 @@ int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out
   }
 }
 
-int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable) {
+int launch_view_starts(void* stream, DView* views, CastHeader* hdr, uint32_t enable) {
   hipLaunchKernelGGL(k_view_starts, dim3((CVX_MAX_VIEWS + 63u) / 64u), dim3(64), 0,
                      (hipStream_t)stream, views, hdr, enable);
   return (int)hipGetLastError();
@@ -1601,11 +1600,6 @@ int launch_merge_pieces(void* stream, const DView* views, const CastHeader* hdr,
                         const void* tmp, void* out, uint32_t stride) {
   hipLaunchKernelGGL(k_merge_pieces, dim3(256, n_views), dim3(256), 0, (hipStream_t)stream, views,
                      hdr, (const float4*)tmp, (float4*)out, stride);
-  return (int)hipGetLastError();
-}
-
-int launch_reset(void* stream, CastHeader* hdr) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, hdr);
   return (int)hipGetLastError();
 }
 

@@ -191,7 +191,6 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
                           uint32_t fmt, void* rec, void* pay, uint32_t R);
 int launch_cast(void* stream, uint32_t variant, bool trace, bool stats, bool out_f64,
                 const CastArgs& a, uint32_t workgroups, uint32_t wg_size);
-int launch_reset(void* stream, CastHeader* hdr);
 // the front-to-back merge of chord pieces into out (views with pieces > 1)
 int launch_merge_pieces(void* stream, const DView* views, const CastHeader* hdr, uint32_t n_views,
                         const void* tmp, void* out, uint32_t stride);
@@ -202,7 +201,7 @@ int launch_merge_pieces(void* stream, const DView* views, const CastHeader* hdr,
 constexpr size_t CVX_SCRATCH_BYTES = sizeof(CastHeader) + CVX_NOALLOC_MAX_VIEWS * sizeof(DView);
 int scratch_address(int device, void** ptr);
 // the shared first leaf of every view whose eye lies inside its canvas
-int launch_view_starts(void* stream, DView* views, const CastHeader* hdr, uint32_t enable);
+int launch_view_starts(void* stream, DView* views, CastHeader* hdr, uint32_t enable);
 // one level of a stroke's walk (cvx_stroke.hip); items == nullptr: the roots;
 // merge = 1: find cells to merge instead of painting and splitting
 int launch_stroke_visit(void* stream, const StrokeItem* items, uint32_t n, const StrokeArgs& a,

@@ -101,6 +101,7 @@ class cvx_render_opts(ctypes.Structure):
                 ("single_queue", ctypes.c_uint32), ("per_ray_start", ctypes.c_uint32),
                 ("wide_offsets", ctypes.c_uint32), ("rays_per_wave", ctypes.c_uint32),
                 ("refill_min", ctypes.c_uint32), ("chord_pieces", ctypes.c_uint32),
+                ("cast_events", ctypes.c_void_p),
                 ("trace", ctypes.POINTER(cvx_trace)), ("stats", ctypes.c_void_p)]
 
 
@@ -363,8 +364,9 @@ def cvx_validate_views(views, descs):
 def make_opts(variant="fp32_rebased", tile=(0, 0), workgroups=0, wg_size=0, use_graph=False,
               out_f64=False, trace=None, stats_ptr=0, top_lookup=0, single_queue=0,
               per_ray_start=0, wide_offsets=0, rays_per_wave=0, refill_min=0,
-              chord_pieces=0):
+              chord_pieces=0, cast_events=0):
     o = cvx_render_opts()
+    o.cast_events = _vp(int(cast_events)) if cast_events else None
     o.chord_pieces = int(chord_pieces)
     o.wide_offsets = int(wide_offsets)
     o.rays_per_wave = int(rays_per_wave)

@@ -346,6 +346,36 @@ def test_wide_offsets_same_image(sess):
         np.testing.assert_array_equal(img.cpu().numpy(), ref)
 
 
+def test_cast_events_time_the_kernel(sess):
+    """cast_events: the library records the caller's two events around the
+    cast kernel of an eager render; the image is the one a render without
+    them gives, the measured span is positive and no longer than the events
+    the caller records around the whole call, and a graph render rejects
+    them."""
+    import ctypes
+
+    from paper_1704_02724_amd import cvx
+    torch = sess.torch
+    w = configs.tiny(leaf_format=LEAF_RGBA8_F16, W=160, H=96)
+    sess.upload(0, w.canvases[0])
+    ref = sess.render(w.views, "fp32_rebased").cpu().numpy()
+    k0, k1, c0, c1 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+    for e in (k0, k1):
+        e.record(sess.stream)
+    pair = (ctypes.c_void_p * 2)(k0.cuda_event, k1.cuda_event)
+    for _ in range(2):
+        c0.record(sess.stream)
+        img = sess.render(w.views, "fp32_rebased", cast_events=ctypes.addressof(pair))
+        c1.record(sess.stream)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(img.cpu().numpy(), ref)
+        kernel, call = k0.elapsed_time(k1), c0.elapsed_time(c1)
+        assert 0.0 < kernel <= call
+    with pytest.raises(cvx.CvxError) as e:
+        sess.render(w.views, "fp32_rebased", use_graph=True, cast_events=ctypes.addressof(pair))
+    assert e.value.code == cvx.CVX_ERR_INVALID_ARG
+
+
 def test_lane_refill_same_image(sess):
     """Lane refill (rays_per_wave > 64: finished lanes take the next rays of a
     work item of several tiles once refill_min lanes wait) runs the same
