@@ -682,5 +682,37 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def reap_children():
+    """Ends the run with no process of its own left behind: lists any child
+    process still alive (the compilers the oracle and the canvas builder may
+    start have exited by then, so normally none), then terminates and waits
+    for each."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    if not kids:
+        return
+    def name(k):
+        try:
+            return f"{k.pid} {' '.join(k.cmdline()[:4])} ({k.status()})"
+        except psutil.Error:
+            return f"{k.pid} (gone)"
+    log("child processes left at exit: " + ", ".join(name(k) for k in kids))
+    for k in kids:
+        try:
+            k.terminate()
+        except psutil.NoSuchProcess:
+            pass
+    _, alive = psutil.wait_procs(kids, timeout=5)
+    for k in alive:
+        k.kill()
+    psutil.wait_procs(alive, timeout=5)
+
+
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    finally:
+        reap_children()

@@ -471,6 +471,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   uint32_t ub = 0;
   uint32_t step = 0;
   uint32_t end_Nn = 0, end_nc = 0, end_dep = 0;  // the move the ray ended on
+  // the ray ended at the canvas boundary or the opacity stop; it leaves the
+  // loop at the top of the next iteration (one exit, so the loop-carried
+  // values need no copies for a second one)
+  bool done = false;
   // SPLIT: s-value of the piece's end and its error bound (BIGF: no end)
   float s_end = BIGF, e_end = 0.0f;
   // FP64 rebuild of the base frame at ray parameter te (q = FP64 point); the
@@ -546,12 +550,13 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
     step = 0;
     end_Nn = end_nc = end_dep = 0;
+    done = false;
   };
   // flags, colour and counts of the ray that ended
   auto finish = [&]() __attribute__((always_inline)) {
     if (bad)
       out.flags |= CVX_RAYFLAG_BAD_LINK;
-    else if (step >= v.max_steps)
+    else if (!done && step >= v.max_steps)
       out.flags |= CVX_RAYFLAG_STEP_CAP;
     else if (end_Nn >= v.n_nodes && end_nc < (v.R << end_dep))
       out.flags |= CVX_RAYFLAG_BAD_LINK;  // a null link inside the canvas
@@ -562,7 +567,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     out.rgba[3] = 1.0f - T;
     out.T = T;
     out.n = n_rec;
-    out.steps = step + 1;
+    out.steps = done ? step : step + 1;  // a ray that ended left one iteration later
     if (STATS) acc.leaves += n_rec;
   };
   // REFILL: the pixel of the lane's current ray; starting ray i of the job
@@ -619,7 +624,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       if ((uint32_t)__popcll(__ballot(!alive)) >= wait_for) break;
       if (!alive) continue;
     }
-    if (step >= v.max_steps || bad) {
+    if (step >= v.max_steps || bad || done) {
       if constexpr (!REFILL) break;
       finish();
       write_pixel();
@@ -781,18 +786,25 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       const uint32_t Nn = (root || inner) ? sib : link;
       // the canvas boundary has null links (CVX_NONE >= n_nodes) and so would
       // a broken pool: the two are told apart after the loop
-      if (Nn >= v.n_nodes || (use_stop && 1.0f - T >= v.alpha_stop)) {
+      // (bitwise: lane masks, not a branch)
+      const bool stop = (Nn >= v.n_nodes) | (use_stop & (1.0f - T >= v.alpha_stop));
+      if (stop) {
         end_Nn = Nn;
         end_nc = nc;
         end_dep = dep;
-        if constexpr (!REFILL) break;
-        finish();
-        write_pixel();
-        alive = false;
-        continue;
+        if constexpr (REFILL) {
+          finish();
+          write_pixel();
+          alive = false;
+          continue;
+        }
+        done = true;
       }
-      if (STATS) acc.outer += !inner;
-      I = Nn;
+      // a ray that stopped still runs the move below (its results are not
+      // used) with node 0 in place of the neighbour, so that no load leaves
+      // the pool
+      if (STATS) acc.outer += !inner && !stop;
+      I = stop ? 0u : Nn;
       r = ld_rec_t<SMALL>(rec, I);
       pay = ld_pay_t<SMALL>(payp, I);
       c.x = mx ? nc : c.x;
@@ -818,7 +830,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       w <<= m;
       dep -= m;
     }
-    if (need64) {
+    if (need64 && !done) {
       // FP64 rebase at the near face (axis ke) of the current cell
       const int kr = ke < 0 ? 0 : ke;
       const uint32_t cr = get(c, kr);
