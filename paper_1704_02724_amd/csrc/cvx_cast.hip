@@ -65,6 +65,18 @@ __device__ __forceinline__ void set(V3<T>& v, int k, T a) {
   v = V3<T>{k == 0 ? a : u.x, k == 1 ? a : u.y, k == 2 ? a : u.z};
 }
 
+// Per-lane boolean logic on wavefront lane masks: the compare results are
+// combined with scalar instructions instead of being materialised as 0/1 in
+// vector registers (the compiler does the latter for some select shapes).
+__device__ __forceinline__ uint64_t lanes(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+__device__ __forceinline__ bool lane(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Cell indices between true and direction-normalised form (an involution):
+// component k xor all ones when the ray travels down axis k.
+__device__ __forceinline__ V3<uint32_t> flip(V3<uint32_t> c, const V3<bool>& up) {
+  return V3<uint32_t>{c.x ^ (up.x ? 0u : ~0u), c.y ^ (up.y ? 0u : ~0u), c.z ^ (up.z ? 0u : ~0u)};
+}
+
 struct Acc {
   uint32_t rays, leaves, outer, descent, fp64_exit, rebase;
   uint64_t steps, slots;  // loop iterations of the lanes; 64 x the longest lane per tile
@@ -455,6 +467,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   V3<bool> up;
   V3<double> q;
   uint32_t I = 0, dep = 0;
+  // cell indices at depth dep, direction-normalised: c_k xor all ones when
+  // the ray travels down axis k, so that the next cell along the ray is
+  // always c_k + 1 and an arithmetic shift right gives the parent's index
+  // (R 2^max_depth <= 2^30: the sign bit is the direction)
   V3<uint32_t> c;
   uint4 r;
   uint2 pay = make_uint2(0u, 0u);
@@ -482,8 +498,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   auto rebase = [&](double te) __attribute__((always_inline)) {
     if (TRACE) te_last = te;
     const uint32_t d0 = dep;
+    V3<uint32_t> cr = flip(c, up);  // true indices
     bad = bad || !descend_int(rec, v.n_nodes, deep_coords(q, up, v.R, v.max_depth), v.max_depth,
-                              I, dep, c, r);
+                              I, dep, cr, r);
     if (STATS) acc.descent += dep - d0;
     pay = ld_pay_t<SMALL>(payp, I);
     db = dep + DB_MARGIN < v.max_depth ? dep + DB_MARGIN : (v.max_depth > dep ? v.max_depth : dep);
@@ -494,10 +511,11 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     // the rebase term of the bound)
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
-      const double X = (double)get(c, k) * hd + (get(up, k) ? hd : 0.0);  // exact
+      const double X = (double)get(cr, k) * hd + (get(up, k) ? hd : 0.0);  // exact
       const double Tk = (X - slot.at(k)) * slot.at(6 + k);
       set(S0, k, get(tD, k) == 0.0f ? BIGF : (float)ldexp(Tk - te, (int)db));
     }
+    c = flip(cr, up);
     Nk = V3<int32_t>{0, 0, 0};
     s_ent = 0.0f;
     const float beta = ldexpf(tR, (int)db - 50);
@@ -534,6 +552,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     }
     dep = 0;
     start_leaf(v, q, up, I, dep, c, r, shared_start);
+    c = flip(c, up);
     if (STATS) acc.descent += dep;
     pay = make_uint2(0u, 0u);
     db = 0;
@@ -662,10 +681,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         const bool far = diff >= 0.0f;
         const bool sure = __builtin_fabsf(diff) > e_ent + get(eb, k);
         need64 = need64 || !sure;
-        const uint32_t b = (get(up, k) == far) ? 1u : 0u;
+        const uint32_t b = (get(up, k) == far) ? 1u : 0u;  // the child's octant bit
         oct |= b << k;
         set(Nk, k, get(Nk, k) - (far ? 0 : (int32_t)half));
-        set(c, k, 2u * get(c, k) + b);
+        set(c, k, 2u * get(c, k) + (far ? 1u : 0u));  // normalised: the far child is next
       }
       if (!need64) {
         I = r.x + oct;
@@ -679,25 +698,28 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       // undo the speculative update; the FP64 rebase descends from here
       for (int k = 0; k < 3; ++k) {
         const uint32_t ck = get(c, k);
-        const bool far = ((ck & 1u) != 0u) == get(up, k);
+        const bool far = (ck & 1u) != 0u;
         set(Nk, k, get(Nk, k) + (far ? 0 : (int32_t)half));
-        set(c, k, ck >> 1);
+        set(c, k, (uint32_t)((int32_t)ck >> 1));
       }
     } else {
       // ---- leaf: exit face, certified against the error bounds
       const float Smin = __builtin_fminf(S.x, __builtin_fminf(S.y, S.z));
       // exit axis kx (ties to the lower axis), also held one-hot as lane
       // masks mx, my (z when neither) for the selects below
-      bool mx = S.x == Smin;
-      bool my = !mx & (S.y == Smin);
+      const uint64_t bx = lanes(S.x == Smin);
+      bool mx = lane(bx);
+      bool my = lane(lanes(S.y == Smin) & ~bx);
       int kx = mx ? 0 : (my ? 1 : 2);
       const float emin = mx ? eb.x : (my ? eb.y : eb.z);
-      // certified when exactly the two other planes clear the minimum by
-      // more than both bounds (as lane masks: scalar logic, no vector count)
-      const bool s0 = S.x - Smin > eb.x + emin;
-      const bool s1 = S.y - Smin > eb.y + emin;
-      const bool s2 = S.z - Smin > eb.z + emin;
-      const bool cert = (s0 & s1 & !s2) | (s0 & !s1 & s2) | (!s0 & s1 & s2);
+      // certified when the two other planes clear the minimum by more than
+      // both bounds; the minimum's own test is always false (0 against a
+      // positive bound), so this is the majority of the three (lane masks:
+      // scalar logic, no vector count)
+      const uint64_t s0 = lanes(S.x - Smin > eb.x + emin);
+      const uint64_t s1 = lanes(S.y - Smin > eb.y + emin);
+      const uint64_t s2 = lanes(S.z - Smin > eb.z + emin);
+      const bool cert = lane((s0 & s1) | (s2 & (s0 | s1)));
       // exit plane value and bound (the smallest one unless FP64 decides)
       float Sx = Smin, ex = emin;
       if (!cert) {
@@ -708,7 +730,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         int kb = kx;
 #pragma unroll 1
         for (int k = 0; k < 3; ++k) {
-          const double X = (double)get(c, k) * hd + (get(up, k) ? hd : 0.0);
+          const double X = (double)(get(c, k) ^ (get(up, k) ? 0u : ~0u)) * hd +
+                           (get(up, k) ? hd : 0.0);
           const double tt = get(tD, k) == 0.0f ? __builtin_inf() : (X - slot.at(k)) * slot.at(6 + k);
           kb = tt < best ? k : kb;
           best = tt < best ? tt : best;
@@ -740,17 +763,18 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
             cut = true;
           } else {
             const double hd = ldexp(1.0, -(int)dep);
-            const double X = (double)get(c, kx) * hd + (get(up, kx) ? hd : 0.0);
+            const double X = (double)(get(c, kx) ^ (get(up, kx) ? 0u : ~0u)) * hd +
+                             (get(up, kx) ? hd : 0.0);
             cut = (X - slot.at(kx)) * slot.at(6 + kx) > t_end;
           }
         }
         Sl = cut ? s_end : Sx;
       }
       // length precision guard: rebase once the bound on this segment's
-      // length exceeds 2^-10 of the leaf edge (w = 2^(db - dep) base cells);
-      // for a positive float, x > 2^n exactly when its bits exceed those of 2^n
+      // length exceeds 2^-10 of the leaf edge (w = 2^(db - dep) base cells),
+      // compared in leaf edges (a power-of-two scale: exact)
       const float eseg = ex + e_ent;
-      need64 = need64 || __builtin_bit_cast(uint32_t, eseg) > ((db - dep + 117u) << 23);
+      need64 = need64 || ldexpf(eseg, (int)dep - (int)db) > 0x1p-10f;
       float len = ldexpf(Sl - s_ent, (int)dep - (int)db);
       len = len > 0.0f ? len : 0.0f;
       // composite; every visited leaf is recorded: for a ray outside the face
@@ -768,19 +792,21 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       }
       // ---- neighbour across the exit face: sibling, next root or G_3 link
       const bool mz = !mx & !my;
-      const uint32_t ck = mx ? c.x : (my ? c.y : c.z);
+      const uint32_t ck = mx ? c.x : (my ? c.y : c.z);  // normalised
       const uint32_t upk = (ub >> kx) & 1u;
-      const uint32_t nc = ck + 2u * upk - 1u;            // wraps to ~0 below 0
+      const uint32_t nc = ck + 1u;  // normalised index of the next cell on axis kx
       const bool root = dep == 0;
-      // the sibling lies across the face when the cell is even going up
-      // (odd going down); siblings differ in octant bit kx only
-      const bool inner = !root && ((ck ^ upk) & 1u) != 0u;
+      // the sibling lies across the face when the normalised index is even
+      // (the cell is even going up, odd going down); siblings differ in
+      // octant bit kx only
+      const bool inner = !root && (ck & 1u) == 0u;
       uint32_t sib = I ^ (1u << kx);
       if (root) {
         // root array (rare): kept as a branch, not flattened into selects
         asm volatile("");
+        const uint32_t ncr = upk ? nc : ~nc;  // true index; wraps to ~0 below 0
         const uint32_t rs = mx ? 1u : (my ? v.R : v.R * v.R);
-        sib = nc >= v.R ? CVX_NONE : (upk ? I + rs : I - rs);
+        sib = ncr >= v.R ? CVX_NONE : (upk ? I + rs : I - rs);
       }
       const uint32_t link = mx ? r.y : (my ? r.z : r.w);
       const uint32_t Nn = (root || inner) ? sib : link;
@@ -790,7 +816,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       const bool stop = (Nn >= v.n_nodes) | (use_stop & (1.0f - T >= v.alpha_stop));
       if (stop) {
         end_Nn = Nn;
-        end_nc = nc;
+        end_nc = upk ? nc : ~nc;  // true index
         end_dep = dep;
         if constexpr (REFILL) {
           finish();
@@ -807,6 +833,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       I = stop ? 0u : Nn;
       r = ld_rec_t<SMALL>(rec, I);
       pay = ld_pay_t<SMALL>(payp, I);
+      const V3<uint32_t> co = c;
       c.x = mx ? nc : c.x;
       c.y = my ? nc : c.y;
       c.z = mz ? nc : c.z;
@@ -814,18 +841,17 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       e_ent = ex;
       ke = kx;
       // far planes move by one cell on the exit axis, and for a coarser
-      // leaf by the integer number of cells to its far planes:
-      // (mask - lo) = lo ^ mask going up, lo going down
+      // leaf (m levels up) by the integer number of cells to its far planes:
+      // in normalised indices the coarse cell's far plane lies after fine
+      // cell (new | mask), so the plane advances by (new | mask) - old cells
       const uint32_t dL = (r.x & 1u) ? ((r.x >> 1) & 63u) : dep;
       const uint32_t m = dL < dep ? dep - dL : 0u;
       const uint32_t mask = (1u << m) - 1u;
       const uint32_t lw = db - dep;  // w = 2^lw
-      const V3<bool> mk{mx, my, mz};
       for (int k = 0; k < 3; ++k) {
-        const uint32_t ckk = get(c, k);
-        const uint32_t dist = get(up, k) ? (~ckk & mask) : (ckk & mask);
-        set(Nk, k, get(Nk, k) + (int32_t)(((get(mk, k) ? 1u : 0u) + dist) << lw));
-        set(c, k, ckk >> m);
+        const uint32_t cn = get(c, k);
+        set(Nk, k, get(Nk, k) + (int32_t)(((cn | mask) - get(co, k)) << lw));
+        set(c, k, (uint32_t)((int32_t)cn >> m));
       }
       w <<= m;
       dep -= m;
@@ -833,7 +859,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     if (need64 && !done) {
       // FP64 rebase at the near face (axis ke) of the current cell
       const int kr = ke < 0 ? 0 : ke;
-      const uint32_t cr = get(c, kr);
+      const uint32_t cr = get(c, kr) ^ (get(up, kr) ? 0u : ~0u);  // true index
       const double Xp = (double)(get(up, kr) ? cr : cr + 1u) * ldexp(1.0, -(int)dep);
       const double te = (Xp - slot.at(kr)) * slot.at(6 + kr);
       for (int k = 0; k < 3; ++k) set(q, k, k == kr ? Xp : slot.at(k) + te * slot.at(3 + k));
