@@ -444,6 +444,7 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     dv.H = v.H;
     dv.out_off = v.out_offset_px;
     dv.alpha_stop = v.alpha_stop;
+    dv.t_stop = (float)(1.0 - (double)v.alpha_stop);
     dv.tiles_x = (v.W + p.tw - 1) / p.tw;
     uint64_t tiles_y = (v.H + p.th - 1) / p.th;
     // work items before this view: tiles, or with lane refill groups of

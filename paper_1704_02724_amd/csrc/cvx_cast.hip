@@ -483,7 +483,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
   float T = 1.0f;
   V3<float> C{0.f, 0.f, 0.f};
   uint32_t n_rec = 0;
-  int ke = -1;  // axis of the face the current cell was entered through
+  // bit (1, 2 or 4) of the axis of the face the current cell was entered
+  // through; 0 where the ray started inside the canvas
+  uint32_t kbe = 0;
   uint32_t ub = 0;
   uint32_t step = 0;
   uint32_t end_Nn = 0, end_nc = 0, end_dep = 0;  // the move the ray ended on
@@ -563,7 +565,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     T = 1.0f;
     C = V3<float>{0.f, 0.f, 0.f};
     n_rec = 0;
-    ke = en.kin;
+    kbe = en.kin < 0 ? 0u : 1u << en.kin;
     // travel direction bits (x | y<<1 | z<<2) in one opaque register: the
     // exit-axis bit is one bit-field extract, not a chain of selects
     ub = opaque((up.x ? 1u : 0u) | (up.y ? 2u : 0u) | (up.z ? 4u : 0u));
@@ -665,9 +667,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     }
     bool need64 = false;
     if (!leaf) {
-      // ---- refined cell entered through its near face on axis ke: one level.
-      // A refined cell is only reached by a leaf step (ke >= 0), and its
-      // neighbours are of the same depth, so on axis ke the entry value s_ent
+      // ---- refined cell entered through its near face on axis kbe: one level.
+      // A refined cell is only reached by a leaf step (kbe != 0), and its
+      // neighbours are of the same depth, so on axis kbe the entry value s_ent
       // and the mid-plane differ by exactly half a cell in N (>= 1 base cell,
       // far above the bounds): the entry side of that axis needs no test.
       need64 = w < 2u || anypar;
@@ -705,12 +707,13 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     } else {
       // ---- leaf: exit face, certified against the error bounds
       const float Smin = __builtin_fminf(S.x, __builtin_fminf(S.y, S.z));
-      // exit axis kx (ties to the lower axis), also held one-hot as lane
-      // masks mx, my (z when neither) for the selects below
+      // exit axis (ties to the lower axis) as its bit kbit (1, 2, 4), also
+      // held one-hot as lane masks mx, my (z when neither) for the selects
+      // below
       const uint64_t bx = lanes(S.x == Smin);
       bool mx = lane(bx);
       bool my = lane(lanes(S.y == Smin) & ~bx);
-      int kx = mx ? 0 : (my ? 1 : 2);
+      uint32_t kbit = mx ? 1u : (my ? 2u : 4u);
       const float emin = mx ? eb.x : (my ? eb.y : eb.z);
       // certified when the two other planes clear the minimum by more than
       // both bounds; the minimum's own test is always false (0 against a
@@ -727,7 +730,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         // the correctly rounded reciprocal (as the FP64 caster does)
         const double hd = ldexp(1.0, -(int)dep);
         double best = __builtin_inf();
-        int kb = kx;
+        int kb = __builtin_ctz(kbit);
 #pragma unroll 1
         for (int k = 0; k < 3; ++k) {
           const double X = (double)(get(c, k) ^ (get(up, k) ? 0u : ~0u)) * hd +
@@ -736,11 +739,11 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
           kb = tt < best ? k : kb;
           best = tt < best ? tt : best;
         }
-        kx = kb;
+        kbit = 1u << kb;
         mx = kb == 0;
         my = kb == 1;
-        Sx = get(S, kx);
-        ex = get(eb, kx);
+        Sx = get(S, kb);
+        ex = get(eb, kb);
         need64 = true;
         out.flags |= CVX_RAYFLAG_FP64_EXIT;
         if (STATS) acc.fp64_exit++;
@@ -763,6 +766,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
             cut = true;
           } else {
             const double hd = ldexp(1.0, -(int)dep);
+            const int kx = __builtin_ctz(kbit);
             const double X = (double)(get(c, kx) ^ (get(up, kx) ? 0u : ~0u)) * hd +
                              (get(up, kx) ? hd : 0.0);
             cut = (X - slot.at(kx)) * slot.at(6 + kx) > t_end;
@@ -779,7 +783,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       len = len > 0.0f ? len : 0.0f;
       // composite; every visited leaf is recorded: for a ray outside the face
       // band the exact segment is positive even when it rounds to 0 here
-      const float Tn = T * __builtin_amdgcn_exp2f(kappa_of(pay) * len * -1.4426950408889634f);
+      // (kappa len as an FMA with a zero addend: the same rounding as the
+      // product, with the FP16 kappa taken as an operand, no conversion)
+      const float Tn =
+          T * __builtin_amdgcn_exp2f(__builtin_fmaf(kappa_of(pay), len, 0.0f) * -1.4426950408889634f);
       const float a = T - Tn;
       C.x = __builtin_fmaf(a, (float)(pay.x & 0xffu), C.x);
       C.y = __builtin_fmaf(a, (float)((pay.x >> 8) & 0xffu), C.y);
@@ -793,14 +800,14 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       // ---- neighbour across the exit face: sibling, next root or G_3 link
       const bool mz = !mx & !my;
       const uint32_t ck = mx ? c.x : (my ? c.y : c.z);  // normalised
-      const uint32_t upk = (ub >> kx) & 1u;
-      const uint32_t nc = ck + 1u;  // normalised index of the next cell on axis kx
+      const bool upk = (ub & kbit) != 0u;
+      const uint32_t nc = ck + 1u;  // normalised index of the next cell on the exit axis
       const bool root = dep == 0;
       // the sibling lies across the face when the normalised index is even
       // (the cell is even going up, odd going down); siblings differ in
-      // octant bit kx only
+      // the exit axis's octant bit only
       const bool inner = !root && (ck & 1u) == 0u;
-      uint32_t sib = I ^ (1u << kx);
+      uint32_t sib = I ^ kbit;
       if (root) {
         // root array (rare): kept as a branch, not flattened into selects
         asm volatile("");
@@ -813,7 +820,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       // the canvas boundary has null links (CVX_NONE >= n_nodes) and so would
       // a broken pool: the two are told apart after the loop
       // (bitwise: lane masks, not a branch)
-      const bool stop = (Nn >= v.n_nodes) | (use_stop & (1.0f - T >= v.alpha_stop));
+      const bool stop = (Nn >= v.n_nodes) | (use_stop & (T <= v.t_stop));
       if (stop) {
         end_Nn = Nn;
         end_nc = upk ? nc : ~nc;  // true index
@@ -839,7 +846,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       c.z = mz ? nc : c.z;
       s_ent = Sx;
       e_ent = ex;
-      ke = kx;
+      kbe = kbit;
       // far planes move by one cell on the exit axis, and for a coarser
       // leaf (m levels up) by the integer number of cells to its far planes:
       // in normalised indices the coarse cell's far plane lies after fine
@@ -857,8 +864,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       dep -= m;
     }
     if (need64 && !done) {
-      // FP64 rebase at the near face (axis ke) of the current cell
-      const int kr = ke < 0 ? 0 : ke;
+      // FP64 rebase at the near face (axis bit kbe) of the current cell
+      const int kr = kbe == 0u ? 0 : __builtin_ctz(kbe);
       const uint32_t cr = get(c, kr) ^ (get(up, kr) ? 0u : ~0u);  // true index
       const double Xp = (double)(get(up, kr) ? cr : cr + 1u) * ldexp(1.0, -(int)dep);
       const double te = (Xp - slot.at(kr)) * slot.at(6 + kr);

@@ -116,7 +116,7 @@ struct DView {
   uint32_t start_ok, start_node, start_dep;
   uint32_t start_c[3];  // its integer coordinates at start_dep
   uint32_t pieces;      // chord pieces per ray (1: unsplit)
-  uint32_t pad0;
+  float t_stop;         // 1 - alpha_stop, rounded once: the FP32 caster stops once T <= t_stop
 };
 
 // Work queues: the work items (tiles or 64-ray chunks) are split into
