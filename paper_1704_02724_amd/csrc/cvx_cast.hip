@@ -71,6 +71,16 @@ __device__ __forceinline__ void set(V3<T>& v, int k, T a) {
 __device__ __forceinline__ uint64_t lanes(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 __device__ __forceinline__ bool lane(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+// 2 c + b for a per-lane bit given as a lane mask: one add with the mask as
+// carry-in (v_addc_co_u32); the compiler would emit a select and a shift-or.
+// The carry-out is written to a scratch SGPR pair and not used.
+__device__ __forceinline__ uint32_t twice_plus(uint32_t c, uint64_t b) {
+  uint32_t r;
+  uint64_t co;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(co) : "v"(c), "s"(b));
+  return r;
+}
+
 // Cell indices between true and direction-normalised form (an involution):
 // component k xor all ones when the ray travels down axis k.
 __device__ __forceinline__ V3<uint32_t> flip(V3<uint32_t> c, const V3<bool>& up) {
@@ -686,7 +696,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         const uint32_t b = (get(up, k) == far) ? 1u : 0u;  // the child's octant bit
         oct |= b << k;
         set(Nk, k, get(Nk, k) - (far ? 0 : (int32_t)half));
-        set(c, k, 2u * get(c, k) + (far ? 1u : 0u));  // normalised: the far child is next
+        set(c, k, twice_plus(get(c, k), lanes(far)));  // normalised: the far child is next
       }
       if (!need64) {
         I = r.x + oct;
@@ -785,13 +795,14 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       // band the exact segment is positive even when it rounds to 0 here
       // (kappa len as an FMA with a zero addend: the same rounding as the
       // product, with the FP16 kappa taken as an operand, no conversion)
-      const float Tn =
-          T * __builtin_amdgcn_exp2f(__builtin_fmaf(kappa_of(pay), len, 0.0f) * -1.4426950408889634f);
-      const float a = T - Tn;
+      // (the absorbed share a = T - T e as one FMA, T updated in place)
+      const float e =
+          __builtin_amdgcn_exp2f(__builtin_fmaf(kappa_of(pay), len, 0.0f) * -1.4426950408889634f);
+      const float a = __builtin_fmaf(-T, e, T);
+      T = T * e;
       C.x = __builtin_fmaf(a, (float)(pay.x & 0xffu), C.x);
       C.y = __builtin_fmaf(a, (float)((pay.x >> 8) & 0xffu), C.y);
       C.z = __builtin_fmaf(a, (float)((pay.x >> 16) & 0xffu), C.z);
-      T = Tn;
       if (TRACE) record(sk, n_rec, I, len);
       ++n_rec;
       if constexpr (SPLIT) {
