@@ -399,8 +399,8 @@ __device__ __forceinline__ float kappa_of(uint2 p) {
 // analysed in Sec. 6.3):
 //   |S_k - exact| <= ALPHA (S0_k + |N_k| / |d_k|) + beta,  beta = 2^(db-50) tR,
 // ALPHA covering the FP32 roundings of S0, 1/|d|, N and the fused update.
-// Exit = argmin S_k, certified when the other two exceed it by more than the
-// sum of their bounds; otherwise the FP64 face planes decide.  A same-depth
+// Exit = argmin S_k, certified when the lower bounds of the other two exceed
+// its upper bound; otherwise the FP64 face planes decide.  A same-depth
 // step adds the cell width w = 2^(db-dep) to N on the exit axis; a step into a
 // coarser leaf adds the integer distance to its far planes; a refined cell is
 // descended one level per iteration by comparing the entry s with the
@@ -409,8 +409,8 @@ __device__ __forceinline__ float kappa_of(uint2 p) {
 // descent goes below db or cannot be certified.
 // ----------------------------------------------------------------------------
 constexpr float ALPHA = 0x1p-21f;
-// certification bound per plane value: 1.0625 (ALPHA G + beta) plus the 2^-23 G
-// rounding of the FP32 difference (G >= |value|), folded into one fma
+// certification bound per plane value: 1.0625 (ALPHA G + beta) plus 2^-23 G
+// for the FP32 rounding of the comparison (G >= |value|), folded into one fma
 constexpr float ALPHA_C = 0x1p-21f * 1.0625f + 0x1p-23f;
 constexpr float BETA_C = 1.0625f;
 constexpr uint32_t DB_MARGIN = 8;
@@ -725,13 +725,16 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       bool my = lane(lanes(S.y == Smin) & ~bx);
       uint32_t kbit = mx ? 1u : (my ? 2u : 4u);
       const float emin = mx ? eb.x : (my ? eb.y : eb.z);
-      // certified when the two other planes clear the minimum by more than
-      // both bounds; the minimum's own test is always false (0 against a
-      // positive bound), so this is the majority of the three (lane masks:
-      // scalar logic, no vector count)
-      const uint64_t s0 = lanes(S.x - Smin > eb.x + emin);
-      const uint64_t s1 = lanes(S.y - Smin > eb.y + emin);
-      const uint64_t s2 = lanes(S.z - Smin > eb.z + emin);
+      // certified when the lower bounds S_k - eb_k of the two other planes
+      // exceed the upper bound Smin + emin of the minimum: each of the two
+      // FP32 roundings is at most 2^-24 G of its plane, inside the 2^-23 G
+      // each bound carries for it.  The minimum's own test is always false
+      // (Smin - emin <= Smin + emin), so this is the majority of the three
+      // (lane masks: scalar logic, no vector count)
+      const float up_min = Smin + emin;
+      const uint64_t s0 = lanes(S.x - eb.x > up_min);
+      const uint64_t s1 = lanes(S.y - eb.y > up_min);
+      const uint64_t s2 = lanes(S.z - eb.z > up_min);
       const bool cert = lane((s0 & s1) | (s2 & (s0 | s1)));
       // exit plane value and bound (the smallest one unless FP64 decides)
       float Sx = Smin, ex = emin;
