@@ -19,8 +19,10 @@ The line also carries, for the headline workload:
     the chip's, and its algorithmic and measured HBM bytes against 8 TB/s,
   * the CPU oracle timed on the host cores over a bounded seeded sample,
 and under "configs" the same measurements (fewer steps, no CPU leg) for the
-other workloads: the depth-24 stereo pair, the depth-30 zoomed view and the
-batch of 64 views over 8 canvases.
+other workloads: the depth-24 stereo pair, the depth-30 zoomed view, the
+batch of 64 views over 8 canvases, and the depth-24 and depth-30 canvases
+refined with k = 10 (leaves of 10 per stroke radius instead of 4: 0.66 G and
+0.18 G nodes, about 390 and 550 leaves per ray).
 """
 from __future__ import annotations
 
@@ -557,7 +559,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=WORKLOADS)
-    ap.add_argument("--extra", default="depth24,depth30,batch",
+    ap.add_argument("--extra", default="depth24,depth30,batch,depth24_k10,depth30_k10",
                     help="workloads measured after the headline one, reported under 'configs' "
                          "(comma-separated; empty for none)")
     ap.add_argument("--extra-steps", type=int, default=10)

@@ -57,9 +57,12 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        # CVX_ORACLE_LIB: another build of oracle.c (the mutation check in
+        # tests/oracle_mutants.py runs the pins against planted mistakes)
+        path = os.environ.get("CVX_ORACLE_LIB") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build(force=False)
-        lib = ctypes.CDLL(LIB)
+        lib = ctypes.CDLL(path)
         vp = ctypes.c_void_p
         lib.orc_render.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_uint64,
                                    ctypes.c_double, ctypes.c_uint32, vp, vp, vp, vp, vp, vp, vp,

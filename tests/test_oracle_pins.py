@@ -294,6 +294,16 @@ def test_algorithmic_bytes_hand_count():
     # refined cell (+1 level), sibling step
     assert out["n_leaves"][0] == 3
     assert out["alg_bytes"][0] == 16 + 8 * 3 + 4 * (1 + (0 + 1) + 0)
+    # a step that lands two levels deeper: (1,0,1)@1 and its child (2,1,2)@2
+    # are refined, so after (0,0,1)@1 the ray enters (4,3,5)@3 (sibling step,
+    # +2 levels), then (5,3,5)@3 (sibling), then (3,1,2)@2 (an outer face of
+    # the depth-2 parent, one level up)
+    cv3 = trees.from_refinement(
+        1, 3, lambda d, c: d == 0 or (d == 1 and c == (1, 0, 1)) or (d == 2 and c == (2, 1, 2)),
+        lambda d, c: (0.1, 0.2, 0.3, 0.5), LEAF_F64)
+    out = oracle.render([cv3], ray_views([(-1.0, 0.375, 0.625)], [(1.0, 0.0, 0.0)]))
+    assert out["n_leaves"][0] == 4
+    assert out["alg_bytes"][0] == 16 + 8 * 4 + 4 * ((1 + 2) + 1)
 
 
 def test_miss_and_eye_inside():
