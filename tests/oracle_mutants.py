@@ -1,4 +1,4 @@
-"""Planted mistakes in the CPU oracle, each of which its pins must catch.
+"""Planted mistakes in the CPU oracles, each of which their pins must catch.
 
 Every mutant is one textual change to a copy of oracle/oracle.c (it must
 match exactly once).  The copy is compiled like the oracle itself, and
@@ -59,6 +59,46 @@ MUTANTS = [
     ("length sum in leaf units", "res->sum_len += len * h;", "res->sum_len += len;"),
 ]
 
+# Planted mistakes in the stroke oracle (oracle/stroke.py, Python): the
+# mutated source is executed into the module before its pins run.
+STROKE_SRC = os.path.join(ROOT, "oracle", "stroke.py")
+STROKE_PINS = os.path.join(ROOT, "tests", "test_stroke_oracle.py")
+STROKE_MUTANTS = [
+    ("split while the edge is at least radius / k",
+     "if e > hmin and d < max_depth:\n            split.add(cell)",
+     "if e >= hmin and d < max_depth:\n            split.add(cell)"),
+    ("split at the max depth", "if e > hmin and d < max_depth:\n            split.add(cell)",
+     "if e > hmin and d <= max_depth:\n            split.add(cell)"),
+    ("overlap includes touching at distance r",
+     "if _outside(lo, e, box) or not any(_box_dist2(lo, e, s) < s[3] * s[3] for s in stamps):\n"
+     "            out[cell] = pay",
+     "if _outside(lo, e, box) or not any(_box_dist2(lo, e, s) <= s[3] * s[3] for s in stamps):\n"
+     "            out[cell] = pay"),
+    ("centre on the sphere does not take the stroke",
+     "if any(_centre_dist2(lo, e, s) <= s[3] * s[3] for s in stamps):\n"
+     "            out[cell] = paint(pay, fmt, e, rgb, sigma, radius)\n        else:",
+     "if any(_centre_dist2(lo, e, s) < s[3] * s[3] for s in stamps):\n"
+     "            out[cell] = paint(pay, fmt, e, rgb, sigma, radius)\n        else:"),
+    ("colour mix weights swapped", "q[ch] = m * rgb[ch] + (1.0 - m) * q[ch]",
+     "q[ch] = (1.0 - m) * rgb[ch] + m * q[ch]"),
+    ("stroke optical depth not per leaf edge", "kb = sigma * e / radius", "kb = sigma / radius"),
+    ("optical depths not added", "q[3] = kb + kc", "q[3] = max(kb, kc)"),
+    ("child keeps the parent's optical depth (F64)",
+     "return (pay[0], pay[1], pay[2], pay[3] * 0.5)", "return (pay[0], pay[1], pay[2], pay[3])"),
+    ("child optical depth quartered (RGBA8)", "np.float32(_f16_value(pay[4])) * np.float32(0.5)",
+     "np.float32(_f16_value(pay[4])) * np.float32(0.25)"),
+    ("leaf centre taken at the corner", "c = [lo[k] + 0.5 * e - s[k] for k in range(3)]",
+     "c = [lo[k] - s[k] for k in range(3)]"),
+    ("box distance negative inside", "v = max(max(lo[k] - s[k], 0.0), s[k] - (lo[k] + e))",
+     "v = max(lo[k] - s[k], s[k] - (lo[k] + e))"),
+    ("opacity byte from twice the optical depth",
+     "a = int(np.rint(255.0 * (1.0 - math.exp(-kap))))\n    return (_byte(col[0])",
+     "a = int(np.rint(255.0 * (1.0 - math.exp(-2.0 * kap))))\n    return (_byte(col[0])"),
+    ("merged leaf keeps the child's optical depth",
+     "return (child[0], child[1], child[2], child[3] * 2.0)",
+     "return (child[0], child[1], child[2], child[3])"),
+]
+
 UNPINNED = [
     ("exit point kept behind the entry point",
      "if (d[k] > 0.0 && qx[k] < q[k]) qx[k] = q[k];", ""),
@@ -95,10 +135,42 @@ def run_all(mutants=MUTANTS, workers=None):
         return list(ex.map(lambda m: run_one(m[0], m[1], m[2], d), mutants))
 
 
+_STROKE_BOOT = """
+import sys
+sys.path.insert(0, {root!r})
+import oracle.stroke as m
+exec(compile(open({path!r}).read(), {path!r}, "exec"), m.__dict__)
+import pytest
+sys.exit(pytest.main([{pins!r}, "-x", "-q", "-p", "no:cacheprovider"]))
+"""
+
+
+def run_one_stroke(name, old, new, workdir):
+    src = mutate(open(STROKE_SRC).read(), old, new)
+    tag = "".join(ch if ch.isalnum() else "_" for ch in name)
+    path = os.path.join(workdir, tag + ".py")
+    with open(path, "w") as f:
+        f.write(src)
+    boot = _STROKE_BOOT.format(root=ROOT, path=path, pins=STROKE_PINS)
+    r = subprocess.run([sys.executable, "-c", boot], cwd=ROOT, capture_output=True, text=True,
+                       timeout=900)
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return name, r.returncode != 0, (lines[0] if lines else r.stdout.strip().splitlines()[-1])
+
+
+def run_all_stroke(mutants=STROKE_MUTANTS, workers=None):
+    workers = workers or min(8, os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory() as d, cf.ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda m: run_one_stroke(m[0], m[1], m[2], d), mutants))
+
+
 if __name__ == "__main__":
     res = run_all()
     for name, caught, detail in res:
         print(f"{'caught' if caught else 'MISSED'}  {name}: {detail}")
     for name, caught, detail in run_all(UNPINNED):
         print(f"{'caught' if caught else 'unpinned'}  {name}: {detail}")
-    sys.exit(0 if all(c for _, c, _ in res) else 1)
+    res_s = run_all_stroke()
+    for name, caught, detail in res_s:
+        print(f"{'caught' if caught else 'MISSED'}  stroke: {name}: {detail}")
+    sys.exit(0 if all(c for _, c, _ in res + res_s) else 1)
