@@ -37,6 +37,10 @@
  *  - a ray is flagged "near a face" when an entry or exit point lies within
  *    eps_face (root units) of a face plane of that leaf other than the one it
  *    lies on; zero-length segments are dropped.
+ *
+ * Parity unpinned: the clamp in orc_trace that keeps a rounded exit point
+ * from lying behind the entry point on a non-exit axis.  No ray of the pins
+ * or of the workloads reaches it, so no pin fails without it.
  */
 #include <math.h>
 #include <pthread.h>
