@@ -117,13 +117,30 @@ __device__ __forceinline__ void record(Sink& sk, uint32_t n, uint32_t I, double 
   }
 }
 
+// FP64 reciprocal square root and reciprocal: the hardware estimate
+// (v_rsq_f64, v_rcp_f64) refined by two Newton steps in FMA form, within an
+// ulp or two of the correctly rounded value, instead of the IEEE square root
+// and division sequences (several times as many half-rate instructions).
+// rcp_nr(x) for |x| < 2^-1000 (zero included) is +-inf, as 1/x overflows.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;  // exact
+  for (int i = 0; i < 2; ++i) y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  for (int i = 0; i < 2; ++i) r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fabs(x) < 0x1p-1000 ? __builtin_copysign(__builtin_inf(), x) : r;
+}
+
 // FP64 unit direction of pixel (x, y) in the public convention
 // (normalize(fwd + u right + v up), u and v from the pixel centre), no
 // contraction.  The divisions by the image size are products with the
 // view's 2/W and 2/H (each rounded once) and the normalisation multiplies by
-// one reciprocal of the norm: each component stays within a few FP64 ulp of
-// the convention's division form, far inside the 1e-12 band in which
-// crossings count as ambiguous.
+// a reciprocal square root of the squared norm: each component stays within
+// a few FP64 ulp of the convention's division form, far inside the 1e-12
+// band in which crossings count as ambiguous.
 __device__ __forceinline__ V3<double> ray_dir(const DView& v, uint32_t x, uint32_t y) {
 #pragma clang fp contract(off)
   double u = (((double)x + 0.5) * v.two_w - 1.0) * v.tan_x;
@@ -134,7 +151,7 @@ __device__ __forceinline__ V3<double> ray_dir(const DView& v, uint32_t x, uint32
     d[k] = d[k] + w * v.up[k];
     n2 += d[k] * d[k];
   }
-  const double rn = 1.0 / __builtin_sqrt(n2);
+  const double rn = rsq_nr(n2);
   return V3<double>{d[0] * rn, d[1] * rn, d[2] * rn};
 }
 
@@ -145,7 +162,7 @@ struct Entry {
 };
 
 // Slab test of the ray against the canvas box [0, R]^3 (FP64), with the
-// correctly rounded reciprocal direction inv (one division per axis per ray).
+// ray's reciprocal direction inv (rcp_nr, one per axis per ray).
 __device__ __forceinline__ Entry canvas_entry(const V3<double>& o, const V3<double>& d,
                                               const V3<double>& inv, double Rd) {
   Entry e;
@@ -519,8 +536,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     w = 1u << (db - dep);
     const double hd = ldexp(1.0, -(int)dep);
     // rolled: one FP64 plane live at a time; the plane's parameter uses the
-    // ray's correctly rounded reciprocal direction (a few FP64 ulp, inside
-    // the rebase term of the bound)
+    // ray's reciprocal direction (a few FP64 ulp, inside the rebase term of
+    // the bound)
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
       const double X = (double)get(cr, k) * hd + (get(up, k) ? hd : 0.0);  // exact
@@ -624,7 +641,7 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
     const double Rd = (double)opaque_s(v.R);
     const V3<double> d = ray_dir(vr, px, py);
     const V3<double> o{v.o[0], v.o[1], v.o[2]};
-    const V3<double> inv{1.0 / d.x, 1.0 / d.y, 1.0 / d.z};
+    const V3<double> inv{rcp_nr(d.x), rcp_nr(d.y), rcp_nr(d.z)};
     const Entry en = canvas_entry(o, d, inv, Rd);
     out.rgba[0] = out.rgba[1] = out.rgba[2] = out.rgba[3] = 0.0;
     out.flags = 0;
@@ -740,7 +757,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       float Sx = Smin, ex = emin;
       if (!cert) {
         // FP64 decision from the exact face planes, t = (X - o_k) / d_k with
-        // the correctly rounded reciprocal (as the FP64 caster does)
+        // the ray's reciprocal direction (as the FP64 caster does; an ulp or
+        // two changes a decision only inside the 1e-12 face band)
         const double hd = ldexp(1.0, -(int)dep);
         double best = __builtin_inf();
         int kb = __builtin_ctz(kbit);
@@ -1258,7 +1276,7 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   out.steps = 0;
   out.end[0] = out.end[1] = out.end[2] = 0.0;
   if (STATS) acc.rays++;
-  const V3<double> inv{1.0 / d.x, 1.0 / d.y, 1.0 / d.z};
+  const V3<double> inv{rcp_nr(d.x), rcp_nr(d.y), rcp_nr(d.z)};
   const Entry en = canvas_entry(o, d, inv, (double)v.R);
   if (!en.hit) return;
   const V3<bool> up{d.x > 0.0, d.y > 0.0, d.z > 0.0};
@@ -1287,6 +1305,24 @@ __device__ void cast_ray(const DView& v, uint32_t px, uint32_t py, Sink sk, Acc&
   } else {
     cast_local<_Float16, TRACE, STATS>(v, d, en, up, sk, acc, out);
   }
+}
+
+// View table reads through the constant address space: the table is
+// read-only while the kernel runs, so at a uniform index (render mode: a
+// tile never straddles views) the compiler issues scalar loads straight into
+// scalar registers instead of vector loads and a readfirstlane per word.
+typedef const __attribute__((address_space(4))) uint32_t cu32_t;
+__device__ __forceinline__ DView view_const(const DView* views, int i) {
+  const cu32_t* q = (const cu32_t*)(views + i);
+  uint32_t w[sizeof(DView) / 4];
+  for (int j = 0; j < (int)(sizeof(DView) / 4); ++j) w[j] = q[j];
+  DView u;
+  __builtin_memcpy(&u, w, sizeof(DView));
+  return u;
+}
+__device__ __forceinline__ uint64_t view_first_tile(const DView* views, int i) {
+  const cu32_t* q = (const cu32_t*)&views[i].first_tile;
+  return (uint64_t)q[0] | ((uint64_t)q[1] << 32);
 }
 
 // Copy of a view that is the same in every lane (render mode: a tile never
@@ -1334,9 +1370,9 @@ __device__ __forceinline__ void cast_grid(const CastArgs& a) {
       int lo = 0, hi = (int)nv - 1;
       while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (a.views[mid].first_tile <= (uint64_t)w) lo = mid; else hi = mid - 1;
+        if (view_first_tile(a.views, mid) <= (uint64_t)w) lo = mid; else hi = mid - 1;
       }
-      const DView v = uniform_view(a.views[lo]);
+      const DView v = view_const(a.views, lo);
       uint64_t t = (uint64_t)w - v.first_tile;
       uint32_t piece = 0;
       if constexpr (SPLIT) {
