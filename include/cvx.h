@@ -145,7 +145,11 @@ typedef struct {
   uint32_t use_graph;   /* 1: capture the launch in a HIP graph and replay it */
   uint32_t out_f64;     /* FP64_PLAIN only: out is double RGBA instead of float */
   uint32_t top_lookup;  /* 0: ray starts are located through the pool's top-level table;
-                           1: they descend from the root array (same result) */
+                           1: they descend from the root array (same result).  This table,
+                           read through the L2, stands in for top tree levels staged in
+                           LDS (there is no LDS-depth option): the LDS holds each lane's
+                           FP64 ray slot, which lets the render kernel keep 8 wavefronts
+                           per SIMD, and only ray starts read the top levels */
   uint32_t single_queue; /* 0: the tiles are split into 8 contiguous ranges, one per XCD
                             (workgroup i starts on range i mod 8, then helps the others);
                             1: one queue over all tiles (same result) */
