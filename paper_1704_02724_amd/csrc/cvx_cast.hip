@@ -741,6 +741,38 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       bool mx = lane(bx);
       bool my = lane(lanes(S.y == Smin) & ~bx);
       uint32_t kbit = mx ? 1u : (my ? 2u : 4u);
+      // ---- neighbour across the exit face: sibling, next root or G_3 link.
+      // Its record load is issued as soon as the exit axis is known (again
+      // after an FP64 decision), so that its latency overlaps the
+      // certification and the composite instead of stalling the move.
+      uint32_t nc = 0;  // normalised index of the next cell on the exit axis
+      bool upk = false, inner = false;
+      auto neighbour = [&](uint4 rr) __attribute__((always_inline)) -> uint32_t {
+        const uint32_t ck = mx ? c.x : (my ? c.y : c.z);  // normalised
+        upk = (ub & kbit) != 0u;
+        nc = ck + 1u;
+        const bool root = dep == 0;
+        // the sibling lies across the face when the normalised index is even
+        // (the cell is even going up, odd going down); siblings differ in
+        // the exit axis's octant bit only
+        inner = !root && (ck & 1u) == 0u;
+        uint32_t sib = I ^ kbit;
+        if (root) {
+          // root array (rare): kept as a branch, not flattened into selects
+          asm volatile("");
+          const uint32_t ncr = upk ? nc : ~nc;  // true index; wraps to ~0 below 0
+          const uint32_t rs = mx ? 1u : (my ? v.R : v.R * v.R);
+          sib = ncr >= v.R ? CVX_NONE : (upk ? I + rs : I - rs);
+        }
+        const uint32_t link = mx ? rr.y : (my ? rr.z : rr.w);
+        return (root || inner) ? sib : link;
+      };
+      // the canvas boundary has null links (CVX_NONE >= n_nodes) and so would
+      // a broken pool (the two are told apart after the loop); a null
+      // neighbour's load reads node 0 instead
+      uint32_t Nn = neighbour(r);
+      uint32_t In = Nn < v.n_nodes ? Nn : 0u;
+      uint4 rn = ld_rec_t<SMALL>(rec, In);
       const float emin = mx ? eb.x : (my ? eb.y : eb.z);
       // certified when the lower bounds S_k - eb_k of the two other planes
       // exceed the upper bound Smin + emin of the minimum: each of the two
@@ -775,6 +807,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         my = kb == 1;
         Sx = get(S, kb);
         ex = get(eb, kb);
+        Nn = neighbour(ld_rec_t<SMALL>(rec, I));
+        In = Nn < v.n_nodes ? Nn : 0u;
+        rn = ld_rec_t<SMALL>(rec, In);
         need64 = true;
         out.flags |= CVX_RAYFLAG_FP64_EXIT;
         if (STATS) acc.fp64_exit++;
@@ -829,29 +864,8 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       if constexpr (SPLIT) {
         if (cut) break;  // the piece ends inside this leaf (no move, no flags)
       }
-      // ---- neighbour across the exit face: sibling, next root or G_3 link
+      // ---- move to the neighbour (stop: bitwise, lane masks, not a branch)
       const bool mz = !mx & !my;
-      const uint32_t ck = mx ? c.x : (my ? c.y : c.z);  // normalised
-      const bool upk = (ub & kbit) != 0u;
-      const uint32_t nc = ck + 1u;  // normalised index of the next cell on the exit axis
-      const bool root = dep == 0;
-      // the sibling lies across the face when the normalised index is even
-      // (the cell is even going up, odd going down); siblings differ in
-      // the exit axis's octant bit only
-      const bool inner = !root && (ck & 1u) == 0u;
-      uint32_t sib = I ^ kbit;
-      if (root) {
-        // root array (rare): kept as a branch, not flattened into selects
-        asm volatile("");
-        const uint32_t ncr = upk ? nc : ~nc;  // true index; wraps to ~0 below 0
-        const uint32_t rs = mx ? 1u : (my ? v.R : v.R * v.R);
-        sib = ncr >= v.R ? CVX_NONE : (upk ? I + rs : I - rs);
-      }
-      const uint32_t link = mx ? r.y : (my ? r.z : r.w);
-      const uint32_t Nn = (root || inner) ? sib : link;
-      // the canvas boundary has null links (CVX_NONE >= n_nodes) and so would
-      // a broken pool: the two are told apart after the loop
-      // (bitwise: lane masks, not a branch)
       const bool stop = (Nn >= v.n_nodes) | (use_stop & (T <= v.t_stop));
       if (stop) {
         end_Nn = Nn;
@@ -866,11 +880,10 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
         done = true;
       }
       // a ray that stopped still runs the move below (its results are not
-      // used) with node 0 in place of the neighbour, so that no load leaves
-      // the pool
+      // used), on node 0 when its neighbour is null
       if (STATS) acc.outer += !inner && !stop;
-      I = stop ? 0u : Nn;
-      r = ld_rec_t<SMALL>(rec, I);
+      I = In;
+      r = rn;
       pay = ld_pay_t<SMALL>(payp, I);
       const V3<uint32_t> co = c;
       c.x = mx ? nc : c.x;
