@@ -1,6 +1,7 @@
 """GPU parity on the degenerate inputs of the method, against the oracle ray
 by ray: rays exactly along an axis or inside a coordinate plane (zero
-direction components), a canvas that is one leaf, root arrays whose roots are
+direction components), tiny, subnormal and negative-zero components, a
+canvas that is one leaf, root arrays whose roots are
 leaves (steps through the root array) up to the largest root array, optical
 depths of zero and near the half-precision maximum, a stop opacity reached in
 the first segment, the largest view count, every canvas slot at once, and
@@ -72,6 +73,25 @@ def test_axis_aligned_and_planar_rays(sess):
     for v in views:
         d = np.asarray(v["fwd"])
         assert np.count_nonzero(d) == 1                      # exactly axis aligned
+    _parity(sess, [cv], views)
+
+
+def test_tiny_and_signed_zero_direction_components(sess):
+    """The reciprocal directions come from a hardware estimate refined by
+    Newton steps, with components below 2^-1000 taken as +-inf: centre rays
+    with a component of 1e-300, a subnormal 1e-310, 2^-1001 and 2^-999 (on
+    both sides of that cut) and -0.0, from eyes inside and outside the canvas,
+    against the oracle's divisions."""
+    cv = trees.random_tree(1, 6, seed=106, p_split=0.55, max_nodes=20000,
+                           leaf_format=LEAF_RGBA8_F16, kappa_range=(0.0, 4.0))
+    views = []
+    for tiny in (1e-300, 1e-310, 2.0 ** -1001, 2.0 ** -999, -0.0):
+        for e in ((-0.4, 0.37, 0.61), (0.31, 0.47, 0.52)):
+            f = np.array([1.0, tiny, 0.3])
+            views.append(make_view(np.array(e), f, 0.5, 3, 3))
+    views = _offsets(views)
+    for v in views[::2]:
+        assert abs(np.asarray(v["fwd"])[1]) < 1e-290
     _parity(sess, [cv], views)
 
 
