@@ -864,6 +864,9 @@ __device__ void cast_fp32(const DView& v, const RaySlot slot, const V3<double>& 
       if constexpr (SPLIT) {
         if (cut) break;  // the piece ends inside this leaf (no move, no flags)
       }
+      // keeps the move (the first reader of the neighbour's record) after the
+      // composite, so the record load has the whole step to arrive
+      __builtin_amdgcn_sched_barrier(0);
       // ---- move to the neighbour (stop: bitwise, lane masks, not a branch)
       const bool mz = !mx & !my;
       const bool stop = (Nn >= v.n_nodes) | (use_stop & (T <= v.t_stop));
