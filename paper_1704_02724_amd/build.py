@@ -21,9 +21,9 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # machine-level loop-invariant code motion lifts constants of the per-ray
     # setup out of the persistent tile loop, where they stay live through the
-    # whole traversal; without it the FP32 render kernel needs no scratch
-    # (62-63 VGPRs instead of 64 plus 8-12 bytes of spills per lane) with the same
-    # hot-loop instructions
+    # whole traversal; without it the FP32 render kernel needs 61 VGPRs
+    # instead of 64 (earlier versions of the loop spilled 8-12 bytes per lane
+    # with it) and keeps the same hot-loop instructions
     "-mllvm", "-disable-machine-licm",
     # the render loop is bound by vector instruction issue; the scheduler's
     # ILP strategy orders its independent instructions so that more of them
