@@ -157,7 +157,7 @@ def test_depth30_k10_sampled(sess):
     w = configs.depth30(k=10.0)
     assert int(w.canvases[0].max_depth) == 30
     ids = sample_ray_ids(w.views, 16384, 3032)
-    cmp, err, orc, _ = _sampled(sess, w, ids, "fp32_rebased")
+    cmp, err, orc, gpu = _sampled(sess, w, ids, "fp32_rebased")
     deep = int((orc["leaf_depth"] == 30).any(axis=1).sum())
     print(f"depth30 k=10: {cmp['n']} rays, flagged {cmp['flagged']}, "
           f"mismatch {cmp['seq_mismatch']} (flagged included {cmp['seq_mismatch_all']}), "
@@ -167,6 +167,12 @@ def test_depth30_k10_sampled(sess):
     assert cmp["n"] - cmp["flagged"] >= 2048
     assert cmp["seq_mismatch"] == 0, cmp
     assert err <= 1e-3
+    # the flagged rays (the majority here) are outside the bit-exact claim,
+    # but their colour still meets the RGBA bar and nearly all of their leaf
+    # sequences match too (a face crossing within 1e-12 may go either way)
+    # (the traced RGBA equals the timed render's bit for bit, checked above)
+    assert rgba_err(gpu["rgba"], orc["rgba"], ~cmp["ok_mask"]) <= 1e-3
+    assert cmp["seq_mismatch_all"] - cmp["seq_mismatch"] <= 0.01 * cmp["flagged"], cmp
 
 
 def test_depth30_naive_fails_visibly(sess, depth30):
