@@ -40,3 +40,22 @@ def test_profiled_counts_only_for_the_profiled_kernel(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.profiled_counts("fp32_rebased", "depth24") == (None, None)
     assert bench.profiled_counts("fp32_rebased", "no_such_workload") == (None, None)
+
+
+def test_roofline_bound_follows_the_counters():
+    """The bound is the larger of the two measured fractions (vector issue
+    against its peak, HBM bytes against 8 TB/s); both null without a
+    matching profile."""
+    t = 1e-3  # one launch of 1 ms
+    issue_bound = bench.roofline(8e9, t, 0.4e9, 0.6e9, 5e12)
+    assert issue_bound["bound"] == "alu"
+    assert issue_bound["frac"] == round(0.6e9 / t / bench.VALU_PEAK, 4)
+    assert issue_bound["peak"] == round(bench.VALU_PEAK / 1e9, 1)
+    assert issue_bound["hbm_measured_frac"] == round(0.4e9 / t / bench.HBM_PEAK, 4)
+    assert issue_bound["alg_bytes_frac"] == round(8e9 / t / bench.HBM_PEAK, 4)
+    hbm_bound = bench.roofline(8e9, t, 7.9e9, 0.1e9, 5e12)
+    assert hbm_bound["bound"] == "hbm" and hbm_bound["unit"] == "GB/s"
+    assert hbm_bound["frac"] == round(7.9e9 / t / bench.HBM_PEAK, 4)
+    none = bench.roofline(8e9, t, None, None, None)
+    assert none["bound"] is None and none["frac"] is None and none["traffic"] is None
+    assert none["alg_bytes_frac"] == round(8e9 / t / bench.HBM_PEAK, 4)
