@@ -451,9 +451,9 @@ struct RenderStage {
   bool split_ok;           // a split render may use the context's piece buffer
   const char* split_why;   // the error otherwise
   // non-null: the device address of the host staging, copied by k_stage_views
-  // (the header and the views it counts, within copy_bytes, the whole block,
-  // so a replayed graph copies any view count it holds) inside the launch or
-  // graph of graph slot `slot`; null: one runtime copy on the stream, no graph
+  // (copy_bytes, the whole block, so a replayed graph copies any view count
+  // it holds) inside the launch or graph of graph slot `slot`; null: one
+  // runtime copy on the stream, no graph
   const void* src_dev;
   size_t copy_bytes;
   int slot;

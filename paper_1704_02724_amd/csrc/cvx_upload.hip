@@ -276,16 +276,11 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
 }
 
 // A render call's staged header and view table, copied from pinned (mapped)
-// host memory to the device table on the render stream, 16 bytes per thread:
-// the header and as many view records as the staged header counts, at most
-// max16 units (the staging block).  A kernel of the library's own instead of
-// a runtime copy: the runtime's host-to-device copy after the previous
-// render's cast kernel started some 30 us after that kernel ended.
-__global__ void k_stage_views(const uint4* __restrict__ src, uint4* __restrict__ dst,
-                              uint32_t max16) {
-  const uint32_t nv = ((const CastHeader*)src)->n_views;
-  const uint64_t want = (sizeof(CastHeader) + (uint64_t)nv * sizeof(DView)) / 16u;
-  const uint32_t n16 = want < max16 ? (uint32_t)want : max16;
+// host memory to the device table on the render stream, 16 bytes per thread.
+// A kernel of the library's own instead of a runtime copy: the runtime's
+// host-to-device copy after the previous render's cast kernel started some
+// 30 us after that kernel ended.
+__global__ void k_stage_views(const uint4* __restrict__ src, uint4* __restrict__ dst, uint32_t n16) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
