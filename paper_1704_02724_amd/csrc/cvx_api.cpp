@@ -26,11 +26,10 @@ struct GraphKey {
   const void* stats_ptr = nullptr;
   const void* views = nullptr;
   const void* split_tmp = nullptr;
-  const void* stage_src = nullptr;
   bool operator==(const GraphKey& o) const {
     return variant == o.variant && tw == o.tw && th == o.th && wgs == o.wgs && wg == o.wg &&
            item_tiles == o.item_tiles && refill_min == o.refill_min && pieces == o.pieces &&
-           split_tmp == o.split_tmp && stage_src == o.stage_src &&
+           split_tmp == o.split_tmp &&
            trace == o.trace && stats == o.stats && out64 == o.out64 && small == o.small &&
            per_ray_start == o.per_ray_start &&
            out == o.out && stats_ptr == o.stats_ptr && views == o.views;
@@ -43,18 +42,14 @@ struct cvx_ctx {
   int n_cu = 256;
   std::string err;
   DevCanvas canvases[CVX_MAX_CANVASES];
-  // a render call's header and view table (CastHeader, then stage_cap view
-  // records): staged in one of two pinned host blocks, used in turn so that
-  // the host fills one while the stream still reads the other, and copied on
-  // the stream into one device block by k_stage_views (a kernel reading the
-  // mapped host block); staged[b] is recorded after the last use of block b
+  // a render call's header and view table, staged in one pinned host block
+  // and copied by one transfer into one device block: CastHeader, then
+  // stage_cap view records
   void* d_stage = nullptr;
-  void* h_stage[2] = {nullptr, nullptr};
-  void* h_stage_dev[2] = {nullptr, nullptr};  // their device addresses
+  void* h_stage = nullptr;
   size_t stage_cap = 0;
-  hipEvent_t staged[2]{};
-  bool staged_pending[2] = {false, false};
-  int stage_next = 0;
+  hipEvent_t staged{};
+  bool staged_pending = false;
   // chord pieces of split renders: (colour, T) per pixel and piece
   void* d_split = nullptr;
   size_t split_cap = 0;
@@ -64,20 +59,10 @@ struct cvx_ctx {
   void* h_scratch = nullptr;
   hipEvent_t scratch_staged{};
   bool scratch_pending = false;
-  // replayed render graphs, one per host staging block
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  GraphKey gkey[2];
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey;
 };
-
-static_assert(sizeof(cvx::CastHeader) % 16 == 0 && sizeof(cvx::DView) % 16 == 0,
-              "k_stage_views copies 16-byte units");
-
-namespace cvx {
-// cvx_upload.hip: copies `bytes` (a multiple of 16) of a render call's
-// staging from mapped host memory at src to the device table at dst
-int launch_stage_views(void* stream, const void* src, void* dst, size_t bytes);
-}  // namespace cvx
 
 namespace {
 
@@ -104,36 +89,12 @@ void free_canvas(DevCanvas& c) {
   c = DevCanvas();
 }
 
-// (Re)allocates the render staging for cap views: the device block and the
-// two pinned host blocks with their device addresses.  The caller has
-// synchronised the stream (no staged copy is in flight).
-hipError_t alloc_stage(cvx_ctx* ctx, size_t cap) {
-  if (ctx->d_stage) (void)hipFree(ctx->d_stage);
-  ctx->d_stage = nullptr;
-  for (int b = 0; b < 2; ++b) {
-    if (ctx->h_stage[b]) (void)hipHostFree(ctx->h_stage[b]);
-    ctx->h_stage[b] = ctx->h_stage_dev[b] = nullptr;
-    ctx->staged_pending[b] = false;
-  }
-  ctx->stage_cap = 0;
-  const size_t bytes = sizeof(CastHeader) + sizeof(DView) * cap;
-  hipError_t e = hipMalloc(&ctx->d_stage, bytes);
-  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-    e = hipHostMalloc(&ctx->h_stage[b], bytes, hipHostMallocMapped);
-    if (e == hipSuccess) e = hipHostGetDevicePointer(&ctx->h_stage_dev[b], ctx->h_stage[b], 0);
-  }
-  if (e == hipSuccess) ctx->stage_cap = cap;
-  return e;
-}
-
 void drop_graph(cvx_ctx* ctx) {
-  for (int b = 0; b < 2; ++b) {
-    if (ctx->gexec[b]) (void)hipGraphExecDestroy(ctx->gexec[b]);
-    if (ctx->graph[b]) (void)hipGraphDestroy(ctx->graph[b]);
-    ctx->gexec[b] = nullptr;
-    ctx->graph[b] = nullptr;
-    ctx->gkey[b] = GraphKey();
-  }
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->gexec = nullptr;
+  ctx->graph = nullptr;
+  ctx->gkey = GraphKey();
 }
 
 uint32_t leaf_bytes(uint32_t fmt) { return fmt == CVX_LEAF_F64 ? 32u : 8u; }
@@ -203,9 +164,11 @@ int cvx_create(cvx_ctx** out, int hip_device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, hip_device);
   if (e == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
-  if (e == hipSuccess) e = alloc_stage(ctx, 64);
-  for (int b = 0; b < 2 && e == hipSuccess; ++b)
-    e = hipEventCreateWithFlags(&ctx->staged[b], hipEventDisableTiming);
+  const size_t stage0 = sizeof(CastHeader) + 64 * sizeof(DView);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_stage, stage0);
+  if (e == hipSuccess) e = hipHostMalloc(&ctx->h_stage, stage0, 0);
+  if (e == hipSuccess) ctx->stage_cap = 64;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
   // the allocation-free render path: the address of this device's scratch
   // array (looked up once per device, with the device current) and the
   // pinned host copy its calls stage through
@@ -228,10 +191,8 @@ void cvx_destroy(cvx_ctx* ctx) {
   for (auto& c : ctx->canvases) free_canvas(c);
   if (ctx->d_stage) (void)hipFree(ctx->d_stage);
   if (ctx->d_split) (void)hipFree(ctx->d_split);
-  for (int b = 0; b < 2; ++b) {
-    if (ctx->h_stage[b]) (void)hipHostFree(ctx->h_stage[b]);
-    if (ctx->staged[b]) (void)hipEventDestroy(ctx->staged[b]);
-  }
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->staged) (void)hipEventDestroy(ctx->staged);
   if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
   if (ctx->scratch_staged) (void)hipEventDestroy(ctx->scratch_staged);
   delete ctx;
@@ -446,17 +407,10 @@ struct RenderStage {
   CastHeader* h_hdr;
   DView* d_views;
   CastHeader* d_hdr;
-  hipEvent_t staged;  // recorded after the host staging's last use; it is reused only after it
+  hipEvent_t staged;  // recorded after the copy; the host staging is reused only after it
   bool* staged_pending;
   bool split_ok;           // a split render may use the context's piece buffer
   const char* split_why;   // the error otherwise
-  // non-null: the device address of the host staging, copied by k_stage_views
-  // (copy_bytes, the whole block, so a replayed graph copies any view count
-  // it holds) inside the launch or graph of graph slot `slot`; null: one
-  // runtime copy on the stream, no graph
-  const void* src_dev;
-  size_t copy_bytes;
-  int slot;
 };
 
 // Fills the staged views and header, copies them to the device and launches
@@ -519,12 +473,10 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   for (auto& q : H.queue) q.next = 0;
   if (H.total_work >= (1ull << 32)) return fail(ctx, CVX_ERR_INVALID_ARG, "too much work in one call");
   // one transfer; it also zeroes the queue heads for this call
-  if (!st.src_dev) {
-    CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader) + sizeof(DView) * n_views,
-                           hipMemcpyHostToDevice, ctx->stream));
-    CVX_HIP(hipEventRecord(st.staged, ctx->stream));
-    *st.staged_pending = true;
-  }
+  CVX_HIP(hipMemcpyAsync(st.d_hdr, st.h_hdr, sizeof(CastHeader) + sizeof(DView) * n_views,
+                         hipMemcpyHostToDevice, ctx->stream));
+  CVX_HIP(hipEventRecord(st.staged, ctx->stream));
+  *st.staged_pending = true;
 
   CastArgs a{};
   a.views = st.d_views;
@@ -576,13 +528,7 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
     }
   }
   a.split_tmp = merge ? ctx->d_split : nullptr;
-  if (!o.use_graph || tr || !st.src_dev) {
-    if (st.src_dev) {
-      const int se = cvx::launch_stage_views(ctx->stream, st.src_dev, st.d_hdr, st.copy_bytes);
-      if (se != hipSuccess) return hip_fail(ctx, (hipError_t)se, "k_stage_views");
-      CVX_HIP(hipEventRecord(st.staged, ctx->stream));
-      *st.staged_pending = true;
-    }
+  if (!o.use_graph || tr) {
     int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
     if (le != hipSuccess) return hip_fail(ctx, (hipError_t)le, "k_view_starts");
     const hipEvent_t* ev = (const hipEvent_t*)o.cast_events;
@@ -616,18 +562,10 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
   key.out = out_dev;
   key.stats_ptr = o.stats;
   key.views = st.d_views;
-  key.stage_src = st.src_dev;
-  const int sl = st.slot;
-  if (!ctx->gexec[sl] || !(key == ctx->gkey[sl])) {
-    if (ctx->gexec[sl]) (void)hipGraphExecDestroy(ctx->gexec[sl]);
-    if (ctx->graph[sl]) (void)hipGraphDestroy(ctx->graph[sl]);
-    ctx->gexec[sl] = nullptr;
-    ctx->graph[sl] = nullptr;
-    ctx->gkey[sl] = GraphKey();
+  if (!ctx->gexec || !(key == ctx->gkey)) {
+    drop_graph(ctx);
     CVX_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    int le = cvx::launch_stage_views(ctx->stream, st.src_dev, st.d_hdr, st.copy_bytes);
-    if (le == hipSuccess)
-      le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
+    int le = cvx::launch_view_starts(ctx->stream, st.d_views, st.d_hdr, shared_start);
     if (le == hipSuccess)
       le = cvx::launch_cast(ctx->stream, o.variant, false, stats, o.out_f64 != 0, a, p.wgs, p.wg);
     if (le == hipSuccess && merge)
@@ -640,14 +578,11 @@ int render_launch(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_de
       return hip_fail(ctx, (hipError_t)le, "graph capture launch");
     }
     if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
-    ctx->graph[sl] = g;
-    CVX_HIP(hipGraphInstantiate(&ctx->gexec[sl], ctx->graph[sl], nullptr, nullptr, 0));
-    ctx->gkey[sl] = key;
+    ctx->graph = g;
+    CVX_HIP(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+    ctx->gkey = key;
   }
-  CVX_HIP(hipGraphLaunch(ctx->gexec[sl], ctx->stream));
-  // the graph reads the host staging; it is reused once the graph is done
-  CVX_HIP(hipEventRecord(st.staged, ctx->stream));
-  *st.staged_pending = true;
+  CVX_HIP(hipGraphLaunch(ctx->gexec, ctx->stream));
   return CVX_OK;
 }
 
@@ -666,32 +601,28 @@ int cvx_render(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev,
   if (rc) return rc;
 
   CVX_HIP(hipSetDevice(ctx->device));
+  if (ctx->staged_pending) {
+    CVX_HIP(hipEventSynchronize(ctx->staged));
+    ctx->staged_pending = false;
+  }
   if ((size_t)n_views > ctx->stage_cap) {
     CVX_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->d_stage) (void)hipFree(ctx->d_stage);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    ctx->d_stage = ctx->h_stage = nullptr;
+    ctx->stage_cap = 0;
+    const size_t bytes = sizeof(CastHeader) + sizeof(DView) * (size_t)n_views;
+    CVX_HIP(hipMalloc(&ctx->d_stage, bytes));
+    CVX_HIP(hipHostMalloc(&ctx->h_stage, bytes, 0));
+    ctx->stage_cap = (size_t)n_views;
     drop_graph(ctx);
-    CVX_HIP(alloc_stage(ctx, (size_t)n_views));
   }
-  // the host staging blocks are used in turn; this one is refilled once the
-  // launch that last read it is done
-  const int b = ctx->stage_next;
-  ctx->stage_next ^= 1;
-  if (ctx->staged_pending[b]) {
-    CVX_HIP(hipEventSynchronize(ctx->staged[b]));
-    ctx->staged_pending[b] = false;
-  }
-  uint8_t* h = (uint8_t*)ctx->h_stage[b];
+  uint8_t* h = (uint8_t*)ctx->h_stage;
   uint8_t* d = (uint8_t*)ctx->d_stage;
-  const RenderStage st{(DView*)(h + sizeof(CastHeader)),
-                       (CastHeader*)h,
-                       (DView*)(d + sizeof(CastHeader)),
-                       (CastHeader*)d,
-                       ctx->staged[b],
-                       &ctx->staged_pending[b],
-                       true,
-                       "",
-                       ctx->h_stage_dev[b],
-                       sizeof(CastHeader) + sizeof(DView) * ctx->stage_cap,
-                       b};
+  const RenderStage st{(DView*)(h + sizeof(CastHeader)), (CastHeader*)h,
+                       (DView*)(d + sizeof(CastHeader)), (CastHeader*)d,
+                       ctx->staged,                      &ctx->staged_pending,
+                       true,                             ""};
   return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 
@@ -725,10 +656,7 @@ int cvx_render_noalloc(cvx_ctx* ctx, const cvx_view* views, int n_views, void* o
                        ctx->scratch_staged,              &ctx->scratch_pending,
                        false,
                        "cvx_render_noalloc renders whole chords (chord_pieces 1): merging "
-                       "pieces needs a buffer",
-                       nullptr,
-                       0,
-                       -1};
+                       "pieces needs a buffer"};
   return render_launch(ctx, views, n_views, out_dev, o, p, st);
 }
 
@@ -1512,11 +1440,9 @@ int cvx_autotune(cvx_ctx* ctx, const cvx_view* views, int n_views, void* out_dev
   float best_ms = 0.0f;
   bool have = false;
   uint32_t count = 0;
-  // two untimed renders (they also capture the graphs of both host staging
-  // blocks), then reps timed ones
+  // one untimed render (it also captures the graph), then reps timed ones
   auto time_candidate = [&](const cvx_render_opts& o, float& ms) -> int {
     int r = cvx_render(ctx, views, n_views, out_dev, &o);
-    if (r == CVX_OK) r = cvx_render(ctx, views, n_views, out_dev, &o);
     if (r != CVX_OK) return r;
     if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess)
       return hip_fail(ctx, he, "hipEventRecord");

@@ -275,22 +275,4 @@ int launch_relayout_level(void* stream, const uint32_t* order, uint64_t begin, u
   return (int)hipGetLastError();
 }
 
-// A render call's staged header and view table, copied from pinned (mapped)
-// host memory to the device table on the render stream, 16 bytes per thread.
-// A kernel of the library's own instead of a runtime copy: the runtime's
-// host-to-device copy after the previous render's cast kernel started some
-// 30 us after that kernel ended.
-__global__ void k_stage_views(const uint4* __restrict__ src, uint4* __restrict__ dst, uint32_t n16) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-
-int launch_stage_views(void* stream, const void* src, void* dst, size_t bytes) {
-  const uint32_t n16 = (uint32_t)(bytes / 16);
-  const uint32_t blocks = (n16 + 255u) / 256u < 64u ? (n16 + 255u) / 256u : 64u;
-  hipLaunchKernelGGL(k_stage_views, dim3(blocks ? blocks : 1u), dim3(256), 0, (hipStream_t)stream,
-                     (const uint4*)src, (uint4*)dst, n16);
-  return (int)hipGetLastError();
-}
-
 }  // namespace cvx
