@@ -141,3 +141,32 @@ def test_binding_fails_loudly_without_the_library():
                        timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "/nonexistent/libcvx.so is not built" in r.stderr
+
+
+def test_binding_struct_layouts_match_the_header(cvx, tmp_path):
+    """Every ctypes structure of the binding has the C header's size and
+    field offsets (a C program compiled against include/cvx.h prints them)."""
+    import ctypes
+    import subprocess
+    structs = ["cvx_canvas_desc", "cvx_view", "cvx_trace", "cvx_render_opts", "cvx_tune_result",
+               "cvx_edit", "cvx_stroke"]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "cvx.h"', "int main(void) {"]
+    for name in structs:
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in getattr(cvx, name)._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, "-o", str(exe), str(src)])
+    c = {}
+    for ln in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, value = ln.split()
+        c[(name, field)] = int(value)
+    for name in structs:
+        st = getattr(cvx, name)
+        assert ctypes.sizeof(st) == c[(name, "sizeof")], name
+        for field, _ in st._fields_:
+            assert getattr(st, field).offset == c[(name, field)], (name, field)
